@@ -1,0 +1,171 @@
+/* chem_dnn.h - C ABI of the MI355X (gfx950) DNN chemistry update.
+ *
+ * The library replaces stiff chemistry integration by a fully connected
+ * network, per cell, as DeepFlame's ODENet does (paper: arXiv 2508.18969,
+ * Sec. 2 "DeepFlame workflow": the net maps the thermochemical state
+ * (T, p, Y_i) to the chemical change of the cell).  One call of
+ * chem_dnn_step performs, for every cell i of a batch:
+ *
+ *   1. u_s  = (Y_s^lam - 1)/lam                 power (Box-Cox) transform
+ *   2. z    = (x - mu_in)/sigma_in, x = [T, P, u_1..u_S]   Z-score (Sec. 3.3.1)
+ *   3. a_l  = GELU(W_l a_(l-1) + b_l), l < L;  o = W_L a_(L-1) + b_L
+ *            GELU in the tanh form 0.5x(1+tanh(sqrt(2/pi)(x+0.044715x^3)))
+ *            (Sec. 3.3.2); products on matrix cores in the handle's precision
+ *            with FP32 accumulation (mixed precision, Sec. 3.3.1)
+ *   4. delta = o sigma_out + mu_out;  Y*_s = (max(0, Y_s^lam + lam delta_s))^(1/lam)
+ *   5. Yhat = Y + (Y* - Y) in FP64;  Y_new = Yhat / sum(Yhat)   (FP64, Sec. 3.3.1:
+ *            everything outside the network stays in double precision)
+ *   6. optional T_new keeping sum_s Y_s (h_f,s + c_p,s (T - T_ref)) constant.
+ *
+ * Conventions for every entry point
+ *   - Return value: CHEM_DNN_OK or a negative status; nothing throws or exits.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream) and
+ *     runs asynchronously; OK means "enqueued".  Argument errors are detected on
+ *     the host before anything is enqueued.
+ *   - "device" pointers must point to memory of the handle's GPU; "host"
+ *     pointers to host memory.  The library never allocates device memory:
+ *     the caller owns every buffer, including the workspace.
+ *   - Field layout is structure-of-arrays: array[j * ld + i] holds feature or
+ *     species j of cell i, ld >= n.
+ *   - One handle may be used from one stream at a time.
+ */
+#ifndef CHEM_DNN_H
+#define CHEM_DNN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct chem_dnn chem_dnn; /* opaque handle; host memory owned by the library */
+
+enum {
+    CHEM_DNN_OK = 0,
+    CHEM_DNN_EINVAL = -1,      /* bad argument (NULL, negative size, ld < n, shape mismatch) */
+    CHEM_DNN_ENODEV = -2,      /* no HIP device */
+    CHEM_DNN_EWORKSPACE = -3,  /* workspace NULL, misaligned or smaller than required */
+    CHEM_DNN_EUNSUPPORTED = -4,/* device is not gfx950, or network shape not built */
+    CHEM_DNN_EHIP = -5         /* a HIP runtime call or kernel launch failed */
+};
+
+enum {
+    CHEM_DNN_FP32 = 0,    /* FP32 operands (16x16x4 f32 matrix cores) */
+    CHEM_DNN_BF16 = 1,    /* bfloat16 operands, round-to-nearest-even */
+    CHEM_DNN_FP16 = 2,    /* IEEE half operands, round-to-nearest-even */
+    CHEM_DNN_FP8E4M3 = 3  /* OCP FP8 E4M3 operands, saturating RNE, per-layer power-of-two scales */
+};
+
+/* Network and transform description.  All pointers are host pointers; the
+ * arrays are copied by chem_dnn_init and need not outlive it. */
+typedef struct {
+    int32_t n_species;          /* S, 1..32 */
+    int32_t n_layers;           /* L linear layers; this build supports L = 4 */
+    int32_t widths[9];          /* widths[0] = S + 2, widths[L] = S, hidden widths 1..4096 */
+    int32_t precision;          /* CHEM_DNN_FP32 / _BF16 / _FP16 / _FP8E4M3 */
+    double boxcox_lambda;       /* lam > 0 (0.1 in the workloads shipped) */
+    const double *in_mean;      /* [S+2] Z-score mean of x = [T, P, u_1..u_S] */
+    const double *in_std;       /* [S+2] Z-score standard deviation, > 0 */
+    const double *out_mean;     /* [S] mean of the normalised output; NULL -> 0 */
+    const double *out_std;      /* [S] std of the normalised output; NULL -> 1 */
+    const float *act_amax;      /* [L] max |input| of each layer over a calibration set
+                                   (chem_dnn_calibrate); required for FP8, ignored otherwise */
+    const double *thermo_hf;    /* [S] formation enthalpy J/kg; NULL -> no temperature update */
+    const double *thermo_cp;    /* [S] constant c_p J/(kg K); NULL iff thermo_hf is NULL */
+    double t_ref;               /* reference temperature of h_f, K */
+    int64_t max_batch;          /* largest batch of chem_dnn_train_step (0 = no training) */
+} chem_dnn_desc;
+
+/* Bytes of device workspace chem_dnn_init needs for `desc` (packed weights,
+ * biases, scales, constants and, if max_batch > 0, training scratch).
+ * EINVAL for a bad description, EUNSUPPORTED for a shape this build lacks. */
+int32_t chem_dnn_workspace_bytes(const chem_dnn_desc *desc, size_t *bytes);
+
+/* Create a handle on the current HIP device.  params (device, FP32) is the
+ * flat parameter vector [W_1 (out x in, row-major), b_1, ..., W_L, b_L]; it is
+ * packed into the workspace (device, >= chem_dnn_workspace_bytes, 256-byte
+ * aligned), which must stay allocated and unmodified until chem_dnn_destroy.
+ * Packing is enqueued on stream.  *out receives the handle (NULL on error).
+ * ENODEV without a device, EUNSUPPORTED unless the device is gfx950. */
+int32_t chem_dnn_init(const chem_dnn_desc *desc, const float *params, void *workspace,
+                      size_t workspace_bytes, void *stream, chem_dnn **out);
+
+/* Re-pack (and, for FP8, re-scale) the weights from a new FP32 parameter
+ * vector (device), e.g. after training or loading a checkpoint. */
+int32_t chem_dnn_set_params(chem_dnn *h, const float *params, void *stream);
+
+/* One chemistry update of n cells (steps 1-6 above).
+ *   T, P      device FP64 [n]      temperature K, pressure Pa
+ *   Y         device FP64 [S][ld]  mass fractions
+ *   Y_out     device FP64 [S][ld]  new mass fractions; may alias Y
+ *   T_out     device FP64 [n] or NULL; may alias T; needs thermo data
+ *   n_bad     device uint32 or NULL; the number of cells with a non-finite
+ *             input or result, or a non-positive renormalisation sum, is ADDED
+ *             to *n_bad.  Such cells are passed through: Y_out = Y, T_out = T.
+ * n = 0 is a no-op.  Cells are independent: a cell's result does not depend on
+ * the batch it is in. */
+int32_t chem_dnn_step(chem_dnn *h, int64_t n, int64_t ld, const double *T, const double *P,
+                      const double *Y, double *Y_out, double *T_out, uint32_t *n_bad,
+                      void *stream);
+
+/* FP8 calibration: running the FP32-operand network on n cells, writes each
+ * layer's max |input| (device FP32 [L], overwritten) - the act_amax of an FP8
+ * description.  Valid on FP32 handles only (EINVAL otherwise). */
+int32_t chem_dnn_calibrate(chem_dnn *h, int64_t n, int64_t ld, const double *T,
+                           const double *P, const double *Y, float *amax, void *stream);
+
+/* Per-layer scales (host FP32 [L] each): the operand values fed to the matrix
+ * cores are round(a / act_scale[l]) and round(W / w_scale[l]).  Powers of two
+ * for FP8, 1 otherwise.  Synchronises the handle's stream. */
+int32_t chem_dnn_get_scales(chem_dnn *h, float *act_scale, float *w_scale, void *stream);
+
+/* Plain MLP forward in FP32 on feature-major batches (training path):
+ *   x     device FP32 [D][ld]  normalised inputs, D = widths[0]
+ *   out   device FP32 [S][ld]  linear output
+ *   saved device FP32 [sum of hidden widths][ld] pre-activations z_1..z_(L-1)
+ *         (layer after layer), or NULL (then B <= max_batch and the handle's
+ *         scratch holds them).  B = 0 is a no-op. */
+int32_t chem_dnn_mlp_forward(chem_dnn *h, int64_t B, int64_t ld, const float *x,
+                             const float *params, float *out, float *saved, void *stream);
+
+/* Backward of chem_dnn_mlp_forward for dL/d out = grad_out (device FP32
+ * [S][ld]); needs B <= max_batch (gradient scratch).  saved: the
+ * pre-activations of the forward with the same x and params, or NULL to
+ * recompute them from x (activation recomputation).  grad_params
+ * (device FP32, flat like params) is overwritten; grad_x (device FP32 [D][ld])
+ * is written when not NULL.  The batch reduction has a fixed order: results are
+ * bitwise reproducible. */
+int32_t chem_dnn_mlp_backward(chem_dnn *h, int64_t B, int64_t ld, const float *x,
+                              const float *params, const float *saved, const float *grad_out,
+                              float *grad_params, float *grad_x, void *stream);
+
+/* One training step on a batch of B states (B <= max_batch):
+ * steps 1-2 above with the handle's statistics, FP32 forward, loss
+ * L = sum (o - target)^2 / (B S) (target device FP32 [S][ld], the normalised
+ * Box-Cox increment), backward, and one Adam update (beta1 0.9, beta2 0.999,
+ * eps 1e-8, bias-corrected, `step` counts from 1) of params / adam_m / adam_v
+ * (device FP32, flat, updated in place).  grads (device FP32, flat) receives
+ * the gradient; *loss (device FP32) the loss before the update.  The handle's
+ * packed inference weights are NOT refreshed; call chem_dnn_set_params.
+ * recompute != 0 keeps only the inputs and recomputes pre-activations in the
+ * backward. */
+int32_t chem_dnn_train_step(chem_dnn *h, int64_t B, int64_t ld, const double *T,
+                            const double *P, const double *Y, const float *target,
+                            float *params, float *grads, float *adam_m, float *adam_v,
+                            int64_t step, float lr, int32_t recompute, float *loss,
+                            void *stream);
+
+/* Release the handle (host memory only; the caller frees the workspace). */
+int32_t chem_dnn_destroy(chem_dnn *h);
+
+/* Static description of a status code. */
+const char *chem_dnn_strerror(int32_t status);
+
+/* ABI version of this header: 1. */
+int32_t chem_dnn_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CHEM_DNN_H */

@@ -1,0 +1,287 @@
+"""ctypes binding of ``libchemdnn.so`` (declared in ``include/chem_dnn.h``).
+
+Argument marshalling only: every step of the chemistry update and of the
+training step runs in the library's HIP kernels.  PyTorch provides device
+memory (CUDA tensors on ROCm) and the current stream.  Importing this module
+does not need a GPU; creating a handle does, and fails loudly when the
+library is missing or the device is not gfx950.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "libchemdnn.so")
+
+OK, EINVAL, ENODEV, EWORKSPACE, EUNSUPPORTED, EHIP = 0, -1, -2, -3, -4, -5
+FP32, BF16, FP16, FP8E4M3 = 0, 1, 2, 3
+PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp16": FP16, "fp8": FP8E4M3}
+EXPORTS = ("chem_dnn_workspace_bytes", "chem_dnn_init", "chem_dnn_set_params", "chem_dnn_step",
+           "chem_dnn_calibrate", "chem_dnn_get_scales", "chem_dnn_mlp_forward",
+           "chem_dnn_mlp_backward", "chem_dnn_train_step", "chem_dnn_destroy",
+           "chem_dnn_strerror", "chem_dnn_abi_version")
+
+_dp = C.POINTER(C.c_double)
+_fp = C.POINTER(C.c_float)
+
+
+class Desc(C.Structure):
+    _fields_ = [("n_species", C.c_int32), ("n_layers", C.c_int32), ("widths", C.c_int32 * 9),
+                ("precision", C.c_int32), ("boxcox_lambda", C.c_double),
+                ("in_mean", _dp), ("in_std", _dp), ("out_mean", _dp), ("out_std", _dp),
+                ("act_amax", _fp), ("thermo_hf", _dp), ("thermo_cp", _dp), ("t_ref", C.c_double),
+                ("max_batch", C.c_int64)]
+
+
+class ChemDNNError(RuntimeError):
+    def __init__(self, status, what=""):
+        self.status = status
+        super().__init__(f"{what}: {strerror(status)} ({status})")
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            raise RuntimeError(f"{LIB} is missing: build it with "
+                               "`python -m paper_2508_18969_amd.build`")
+        L = C.CDLL(LIB)
+        vp = C.c_void_p
+        i64 = C.c_int64
+        L.chem_dnn_workspace_bytes.argtypes = [C.POINTER(Desc), C.POINTER(C.c_size_t)]
+        L.chem_dnn_init.argtypes = [C.POINTER(Desc), vp, vp, C.c_size_t, vp, C.POINTER(vp)]
+        L.chem_dnn_set_params.argtypes = [vp, vp, vp]
+        L.chem_dnn_step.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp, vp]
+        L.chem_dnn_calibrate.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp]
+        L.chem_dnn_get_scales.argtypes = [vp, _fp, _fp, vp]
+        L.chem_dnn_mlp_forward.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp]
+        L.chem_dnn_mlp_backward.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp, vp]
+        L.chem_dnn_train_step.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp, i64,
+                                          C.c_float, C.c_int32, vp, vp]
+        L.chem_dnn_destroy.argtypes = [vp]
+        L.chem_dnn_strerror.argtypes = [C.c_int32]
+        L.chem_dnn_strerror.restype = C.c_char_p
+        for name in EXPORTS:
+            if name not in ("chem_dnn_strerror",):
+                getattr(L, name).restype = C.c_int32
+        _lib = L
+    return _lib
+
+
+def strerror(status: int) -> str:
+    try:
+        return lib().chem_dnn_strerror(int(status)).decode()
+    except RuntimeError:
+        return f"status {status}"
+
+
+def _check(status, what):
+    if status != OK:
+        raise ChemDNNError(status, what)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _arr(a, ctype):
+    if a is None:
+        return None, None
+    a = np.ascontiguousarray(a, dtype=np.float64 if ctype is C.c_double else np.float32)
+    return a, a.ctypes.data_as(C.POINTER(ctype))
+
+
+def make_desc(widths, precision, in_mean, in_std, out_mean=None, out_std=None, act_amax=None,
+              thermo=None, max_batch=0, lam=0.1):
+    """Fills a Desc; returns (desc, keepalive) - keep the second alive while the
+    desc is in use."""
+    d = Desc()
+    widths = [int(w) for w in widths]
+    d.n_species = widths[-1]
+    d.n_layers = len(widths) - 1
+    for i, w in enumerate(widths):
+        d.widths[i] = w
+    d.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    d.boxcox_lambda = float(lam)
+    keep = []
+    for name, val, ct in (("in_mean", in_mean, C.c_double), ("in_std", in_std, C.c_double),
+                          ("out_mean", out_mean, C.c_double), ("out_std", out_std, C.c_double),
+                          ("act_amax", act_amax, C.c_float)):
+        a, p = _arr(val, ct)
+        keep.append(a)
+        setattr(d, name, p)
+    if thermo is not None:
+        hf, cp, tref = thermo
+        a, p = _arr(hf, C.c_double)
+        b, q = _arr(cp, C.c_double)
+        keep += [a, b]
+        d.thermo_hf, d.thermo_cp, d.t_ref = p, q, float(tref)
+    d.max_batch = int(max_batch)
+    return d, keep
+
+
+def workspace_bytes(desc) -> int:
+    n = C.c_size_t(0)
+    _check(lib().chem_dnn_workspace_bytes(C.byref(desc), C.byref(n)), "chem_dnn_workspace_bytes")
+    return int(n.value)
+
+
+class ChemDNN:
+    """A chemistry-update handle on the current device.
+
+    params: CUDA float32 tensor, flat [W1 (out x in), b1, ..., W4, b4].
+    The workspace is a torch uint8 tensor owned by this object.
+    """
+
+    def __init__(self, widths, precision, params, in_mean, in_std, out_mean=None, out_std=None,
+                 act_amax=None, thermo=None, max_batch=0, lam=0.1):
+        import torch
+        self.widths = tuple(int(w) for w in widths)
+        self.S = self.widths[-1]
+        self.L = len(self.widths) - 1
+        self.precision = precision
+        self.thermo = thermo is not None
+        desc, keep = make_desc(self.widths, precision, in_mean, in_std, out_mean, out_std,
+                               act_amax, thermo, max_batch, lam)
+        nbytes = workspace_bytes(desc)
+        dev = params.device
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        base = self.workspace.data_ptr()
+        off = (-base) % 256
+        self._ws_ptr = base + off
+        self._ws_bytes = nbytes
+        h = C.c_void_p()
+        _check(lib().chem_dnn_init(C.byref(desc), _ptr(params), C.c_void_p(self._ws_ptr),
+                                   C.c_size_t(nbytes), _stream(), C.byref(h)), "chem_dnn_init")
+        self._h = h
+        del keep
+
+    # -- inference --------------------------------------------------------
+    def step(self, T, P, Y, Y_out=None, T_out=None, n_bad=None):
+        """Chemistry update of n cells (T, P: float64 [n]; Y: float64 [S][ld])."""
+        import torch
+        n = int(T.shape[0])
+        ld = int(Y.stride(0)) if Y.dim() == 2 else n
+        if Y_out is None:
+            Y_out = torch.empty_like(Y)
+        if T_out is None and self.thermo:
+            T_out = torch.empty_like(T)
+        _check(lib().chem_dnn_step(self._h, n, ld, _ptr(T), _ptr(P), _ptr(Y), _ptr(Y_out),
+                                   _ptr(T_out), _ptr(n_bad), _stream()), "chem_dnn_step")
+        return Y_out, T_out
+
+    def calibrate(self, T, P, Y):
+        """Per-layer input max |a| (CUDA float32 [L]) for an FP8 description."""
+        import torch
+        amax = torch.empty(self.L, dtype=torch.float32, device=T.device)
+        n = int(T.shape[0])
+        ld = int(Y.stride(0))
+        _check(lib().chem_dnn_calibrate(self._h, n, ld, _ptr(T), _ptr(P), _ptr(Y), _ptr(amax),
+                                        _stream()), "chem_dnn_calibrate")
+        return amax
+
+    def scales(self):
+        a = (C.c_float * self.L)()
+        w = (C.c_float * self.L)()
+        _check(lib().chem_dnn_get_scales(self._h, a, w, _stream()), "chem_dnn_get_scales")
+        return np.array(a[:]), np.array(w[:])
+
+    def set_params(self, params):
+        _check(lib().chem_dnn_set_params(self._h, _ptr(params), _stream()), "chem_dnn_set_params")
+
+    # -- training ---------------------------------------------------------
+    def mlp_forward(self, x, params, saved=None):
+        import torch
+        B = int(x.shape[1])
+        ld = int(x.stride(0))
+        out = torch.empty((self.S, B), dtype=torch.float32, device=x.device)
+        if out.stride(0) != ld:
+            out = torch.empty((self.S, ld), dtype=torch.float32, device=x.device)[:, :B]
+        _check(lib().chem_dnn_mlp_forward(self._h, B, ld, _ptr(x), _ptr(params), _ptr(out),
+                                          _ptr(saved), _stream()), "chem_dnn_mlp_forward")
+        return out
+
+    def mlp_backward(self, x, params, saved, grad_out, want_grad_x=False):
+        import torch
+        B = int(x.shape[1])
+        ld = int(x.stride(0))
+        gp = torch.empty_like(params)
+        gx = torch.empty((x.shape[0], ld), dtype=torch.float32, device=x.device)[:, :B] \
+            if want_grad_x else None
+        _check(lib().chem_dnn_mlp_backward(self._h, B, ld, _ptr(x), _ptr(params), _ptr(saved),
+                                           _ptr(grad_out), _ptr(gp), _ptr(gx), _stream()),
+               "chem_dnn_mlp_backward")
+        return gp, gx
+
+    def train_step(self, T, P, Y, target, params, grads, adam_m, adam_v, step, lr=1e-3,
+                   recompute=False, loss=None):
+        import torch
+        B = int(T.shape[0])
+        ld = int(Y.stride(0))
+        if loss is None:
+            loss = torch.empty(1, dtype=torch.float32, device=T.device)
+        _check(lib().chem_dnn_train_step(self._h, B, ld, _ptr(T), _ptr(P), _ptr(Y), _ptr(target),
+                                         _ptr(params), _ptr(grads), _ptr(adam_m), _ptr(adam_v),
+                                         int(step), float(lr), int(bool(recompute)), _ptr(loss),
+                                         _stream()), "chem_dnn_train_step")
+        return loss
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().chem_dnn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def hidden_total(widths):
+    return sum(widths[1:-1])
+
+
+def autograd_function():
+    """torch.autograd.Function whose forward and backward are the library's
+    MLP kernels.  Torch only sequences the calls."""
+    import torch
+
+    class ChemMLPFunction(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, x, params, handle, recompute=False):
+            B = x.shape[1]
+            saved = None
+            if not recompute:
+                saved = torch.empty((hidden_total(handle.widths), B), dtype=torch.float32,
+                                    device=x.device)
+            out = handle.mlp_forward(x, params, saved)
+            ctx.handle = handle
+            if recompute:
+                ctx.save_for_backward(x, params)
+            else:
+                ctx.save_for_backward(x, params, saved)
+            return out
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            tensors = ctx.saved_tensors
+            x, params = tensors[0], tensors[1]
+            saved = tensors[2] if len(tensors) > 2 else None
+            go = grad_out.contiguous()
+            gp, gx = ctx.handle.mlp_backward(x, params, saved, go, want_grad_x=ctx.needs_input_grad[0])
+            return gx, gp, None, None
+
+    return ChemMLPFunction

@@ -1,0 +1,369 @@
+// C ABI of the chemistry-update library: argument checking, workspace
+// layout, weight packing and kernel launches.  No device allocation happens
+// here; every device buffer is the caller's.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+
+#include "../../include/chem_dnn.h"
+#include "internal.h"
+#include "train.h"
+
+using namespace chemdnn;
+
+struct chem_dnn {
+  int S, L, D, H[3], prec;
+  int widths[5];
+  NetLayout lay;
+  int dev, n_cu;
+  uint8_t *ws;
+  size_t ws_bytes;
+  // device sub-buffers
+  float *fc;
+  double *dc;
+  uint32_t *amax_bits;
+  float *bias[4];
+  void *wpack[4];
+  TrainScratch tr;
+  int64_t max_batch;
+  int thermo;
+  // host copies kept alive for the asynchronous uploads
+  float hfc[FConst::N];
+  double hdc[DConst::N];
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+int32_t hip_status(hipError_t e) { return e == hipSuccess ? CHEM_DNN_OK : CHEM_DNN_EHIP; }
+
+// Offsets of every sub-buffer inside the workspace.
+struct WsPlan {
+  size_t fc, dc, amax, bias[4], w[4], train, total;
+};
+
+int32_t check_desc(const chem_dnn_desc *d) {
+  if (!d) return CHEM_DNN_EINVAL;
+  const int S = d->n_species, L = d->n_layers;
+  if (S < 1 || S > 30) return CHEM_DNN_EINVAL;
+  if (L < 1 || L > 8) return CHEM_DNN_EINVAL;
+  if (d->widths[0] != S + 2 || d->widths[L] != S) return CHEM_DNN_EINVAL;
+  for (int l = 1; l < L; ++l)
+    if (d->widths[l] < 1 || d->widths[l] > 4096) return CHEM_DNN_EINVAL;
+  if (d->precision < CHEM_DNN_FP32 || d->precision > CHEM_DNN_FP8E4M3) return CHEM_DNN_EINVAL;
+  if (!(d->boxcox_lambda > 0.0) || !isfinite(d->boxcox_lambda)) return CHEM_DNN_EINVAL;
+  if (!d->in_mean || !d->in_std) return CHEM_DNN_EINVAL;
+  for (int f = 0; f < S + 2; ++f)
+    if (!(d->in_std[f] > 0.0) || !isfinite(d->in_mean[f]) || !isfinite(d->in_std[f]))
+      return CHEM_DNN_EINVAL;
+  if ((d->thermo_hf == nullptr) != (d->thermo_cp == nullptr)) return CHEM_DNN_EINVAL;
+  if (d->precision == CHEM_DNN_FP8E4M3 && !d->act_amax) return CHEM_DNN_EINVAL;
+  if (d->max_batch < 0) return CHEM_DNN_EINVAL;
+  if (L != 4) return CHEM_DNN_EUNSUPPORTED;
+  return CHEM_DNN_OK;
+}
+
+int32_t plan(const chem_dnn_desc *d, NetLayout *lay, WsPlan *p) {
+  int32_t st = check_desc(d);
+  if (st) return st;
+  if (!find_layout(d->precision, d->widths[1], d->widths[2], d->widths[3], lay))
+    return CHEM_DNN_EUNSUPPORTED;
+  size_t off = 0;
+  p->fc = off; off = align_up(off + FConst::N * sizeof(float));
+  p->dc = off; off = align_up(off + DConst::N * sizeof(double));
+  p->amax = off; off = align_up(off + 8 * sizeof(uint32_t));
+  for (int l = 0; l < 4; ++l) {
+    p->bias[l] = off;
+    off = align_up(off + (size_t)lay->R[l] * 16 * sizeof(float));
+  }
+  for (int l = 0; l < 4; ++l) {
+    p->w[l] = off;
+    off = align_up(off + (size_t)lay->R[l] * 16 * lay->NQ[l] * lay->KS * lay->EB);
+  }
+  p->train = off;
+  off += train_scratch_bytes(d->widths, d->max_batch);
+  p->total = align_up(off);
+  return CHEM_DNN_OK;
+}
+
+int32_t current_device(int *dev, int *n_cu) {
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count < 1) return CHEM_DNN_ENODEV;
+  if (hipGetDevice(dev) != hipSuccess) return CHEM_DNN_ENODEV;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, *dev) != hipSuccess) return CHEM_DNN_EHIP;
+  if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return CHEM_DNN_EUNSUPPORTED;
+  *n_cu = prop.multiProcessorCount;
+  return CHEM_DNN_OK;
+}
+
+// Power-of-two FP8 activation scale of one layer from its calibration amax.
+double act_scale_of(float amax) {
+  double a = (double)amax;
+  if (!(a > 0.0) || !isfinite(a)) return 1.0;
+  int e;
+  double m = frexp(a / 448.0, &e);
+  return ldexp(1.0, m == 0.5 ? e - 1 : e);
+}
+
+size_t param_offset(const int *widths, int layer, bool bias) {
+  size_t off = 0;
+  for (int l = 0; l < layer; ++l) off += (size_t)widths[l] * widths[l + 1] + widths[l + 1];
+  if (bias) off += (size_t)widths[layer] * widths[layer + 1];
+  return off;
+}
+
+int32_t pack_params(chem_dnn *h, const float *params, hipStream_t s) {
+  const bool fp8 = h->prec == CHEM_DNN_FP8E4M3;
+  hipError_t e = hipSuccess;
+  e = launch_fill_u32(h->amax_bits, 0u, 4, s);
+  for (int l = 0; l < 4 && e == hipSuccess; ++l)
+    if (fp8)
+      e = launch_weight_amax(params + param_offset(h->widths, l, false),
+                             (int64_t)h->widths[l] * h->widths[l + 1], h->amax_bits + l, s);
+  if (e == hipSuccess) e = launch_pow2_scales(h->amax_bits, h->fc, 4, fp8 ? 1 : 0, s);
+  static const int fmt_of[4] = {0, 1, 2, 3};
+  for (int l = 0; l < 4 && e == hipSuccess; ++l) {
+    const int N = h->widths[l + 1], K = h->widths[l];
+    const int rowshift = (l == 3) ? 2 : 0;
+    const int ks = h->lay.KS;
+    e = launch_pack(params + param_offset(h->widths, l, false), N, K, rowshift, h->lay.R[l],
+                    h->lay.NQ[l], ks, fmt_of[h->prec], h->fc + FConst::WSCALE + l, h->wpack[l], s);
+    if (e == hipSuccess)
+      e = launch_pad_bias(params + param_offset(h->widths, l, true), N, rowshift,
+                          h->lay.R[l] * 16, h->bias[l], s);
+  }
+  return hip_status(e);
+}
+
+StepArgs step_args(chem_dnn *h, int64_t n, int64_t ld, const double *T, const double *P,
+                   const double *Y, double *Y_out, double *T_out, uint32_t *n_bad) {
+  StepArgs a;
+  a.T = T; a.P = P; a.Y = Y; a.Y_out = Y_out; a.T_out = T_out; a.n_bad = n_bad;
+  a.n = n; a.ld = ld;
+  a.ntiles = (n + h->lay.MC - 1) / h->lay.MC;
+  for (int l = 0; l < 4; ++l) { a.w[l] = h->wpack[l]; a.b[l] = h->bias[l]; }
+  a.fc = h->fc; a.dc = h->dc;
+  a.amax = nullptr;
+  a.S = h->S;
+  a.thermo = h->thermo;
+  return a;
+}
+
+int grid_for(const chem_dnn *h, int64_t ntiles) {
+  int64_t g = ntiles < h->n_cu ? ntiles : h->n_cu;
+  return (int)(g < 1 ? 1 : g);
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t chem_dnn_abi_version(void) { return 1; }
+
+const char *chem_dnn_strerror(int32_t st) {
+  switch (st) {
+    case CHEM_DNN_OK: return "ok";
+    case CHEM_DNN_EINVAL: return "invalid argument";
+    case CHEM_DNN_ENODEV: return "no HIP device";
+    case CHEM_DNN_EWORKSPACE: return "workspace missing, misaligned or too small";
+    case CHEM_DNN_EUNSUPPORTED: return "unsupported device or network shape";
+    case CHEM_DNN_EHIP: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+int32_t chem_dnn_workspace_bytes(const chem_dnn_desc *desc, size_t *bytes) {
+  if (!bytes) return CHEM_DNN_EINVAL;
+  NetLayout lay;
+  WsPlan p;
+  int32_t st = plan(desc, &lay, &p);
+  if (st) return st;
+  *bytes = p.total;
+  return CHEM_DNN_OK;
+}
+
+int32_t chem_dnn_init(const chem_dnn_desc *d, const float *params, void *workspace,
+                      size_t workspace_bytes, void *stream, chem_dnn **out) {
+  if (!out) return CHEM_DNN_EINVAL;
+  *out = nullptr;
+  NetLayout lay;
+  WsPlan p;
+  int32_t st = plan(d, &lay, &p);
+  if (st) return st;
+  if (!params) return CHEM_DNN_EINVAL;
+  if (!workspace || ((uintptr_t)workspace % kAlign) || workspace_bytes < p.total)
+    return CHEM_DNN_EWORKSPACE;
+  int dev = 0, n_cu = 0;
+  st = current_device(&dev, &n_cu);
+  if (st) return st;
+  if (lay.prepare() != hipSuccess) return CHEM_DNN_EHIP;
+  if (d->max_batch > 0 && train_prepare() != hipSuccess) return CHEM_DNN_EHIP;
+
+  chem_dnn *h = new (std::nothrow) chem_dnn();
+  if (!h) return CHEM_DNN_EHIP;
+  h->S = d->n_species;
+  h->L = d->n_layers;
+  h->D = d->widths[0];
+  for (int l = 0; l < 5; ++l) h->widths[l] = d->widths[l];
+  for (int l = 0; l < 3; ++l) h->H[l] = d->widths[l + 1];
+  h->prec = d->precision;
+  h->lay = lay;
+  h->dev = dev;
+  h->n_cu = n_cu;
+  h->ws = (uint8_t *)workspace;
+  h->ws_bytes = workspace_bytes;
+  h->fc = (float *)(h->ws + p.fc);
+  h->dc = (double *)(h->ws + p.dc);
+  h->amax_bits = (uint32_t *)(h->ws + p.amax);
+  for (int l = 0; l < 4; ++l) {
+    h->bias[l] = (float *)(h->ws + p.bias[l]);
+    h->wpack[l] = h->ws + p.w[l];
+  }
+  h->max_batch = d->max_batch;
+  train_scratch_layout(&h->tr, h->ws + p.train, d->widths, d->max_batch);
+  h->thermo = d->thermo_hf ? 1 : 0;
+
+  // constants
+  const double lam = d->boxcox_lambda;
+  memset(h->hfc, 0, sizeof(h->hfc));
+  memset(h->hdc, 0, sizeof(h->hdc));
+  for (int s = 0; s < h->S; ++s) {
+    const int f = s + 2;
+    const double mu = d->in_mean[f], sd = d->in_std[f];
+    h->hfc[FConst::ZA + f] = (float)(1.0 / (lam * sd));
+    h->hfc[FConst::ZC + f] = (float)(-(1.0 / lam + mu) / sd);
+    const double om = d->out_mean ? d->out_mean[s] : 0.0;
+    const double os = d->out_std ? d->out_std[s] : 1.0;
+    h->hfc[FConst::PA + f] = (float)(lam * os);
+    h->hfc[FConst::PB + f] = (float)(lam * om);
+    if (h->thermo) {
+      h->hdc[DConst::HF + f] = d->thermo_hf[s];
+      h->hdc[DConst::CP + f] = d->thermo_cp[s];
+    }
+  }
+  for (int l = 0; l < 4; ++l) {
+    const double sa = (h->prec == CHEM_DNN_FP8E4M3) ? act_scale_of(d->act_amax[l]) : 1.0;
+    h->hfc[FConst::ASCALE + l] = (float)sa;
+    h->hfc[FConst::INV_SA + l] = (float)(1.0 / sa);
+    h->hfc[FConst::WSCALE + l] = 1.0f;
+    h->hfc[FConst::SOUT + l] = (float)sa;
+  }
+  h->hfc[FConst::LAM] = (float)lam;
+  h->hfc[FConst::INV_LAM] = (float)(1.0 / lam);
+  h->hdc[DConst::T_MU] = d->in_mean[0];
+  h->hdc[DConst::T_IS] = 1.0 / d->in_std[0];
+  h->hdc[DConst::P_MU] = d->in_mean[1];
+  h->hdc[DConst::P_IS] = 1.0 / d->in_std[1];
+  h->hdc[DConst::T_REF] = d->t_ref;
+  h->hdc[DConst::LAM] = lam;
+
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(h->fc, h->hfc, sizeof(h->hfc), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(h->dc, h->hdc, sizeof(h->hdc), hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) {
+    delete h;
+    return CHEM_DNN_EHIP;
+  }
+  st = pack_params(h, params, s);
+  if (st) {
+    delete h;
+    return st;
+  }
+  // the host staging arrays must not be released before the copies finish
+  if (hipStreamSynchronize(s) != hipSuccess) {
+    delete h;
+    return CHEM_DNN_EHIP;
+  }
+  *out = h;
+  return CHEM_DNN_OK;
+}
+
+int32_t chem_dnn_set_params(chem_dnn *h, const float *params, void *stream) {
+  if (!h || !params) return CHEM_DNN_EINVAL;
+  return pack_params(h, params, (hipStream_t)stream);
+}
+
+int32_t chem_dnn_step(chem_dnn *h, int64_t n, int64_t ld, const double *T, const double *P,
+                      const double *Y, double *Y_out, double *T_out, uint32_t *n_bad,
+                      void *stream) {
+  if (!h || n < 0 || ld < n) return CHEM_DNN_EINVAL;
+  if (n == 0) return CHEM_DNN_OK;
+  if (!T || !P || !Y || !Y_out) return CHEM_DNN_EINVAL;
+  if (T_out && !h->thermo) return CHEM_DNN_EINVAL;
+  StepArgs a = step_args(h, n, ld, T, P, Y, Y_out, T_out, n_bad);
+  return hip_status(h->lay.step(a, grid_for(h, a.ntiles), (hipStream_t)stream));
+}
+
+int32_t chem_dnn_calibrate(chem_dnn *h, int64_t n, int64_t ld, const double *T, const double *P,
+                           const double *Y, float *amax, void *stream) {
+  if (!h || n < 0 || ld < n || !amax) return CHEM_DNN_EINVAL;
+  if (h->prec != CHEM_DNN_FP32 || !h->lay.calib) return CHEM_DNN_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = launch_fill_u32((uint32_t *)amax, 0u, 4, s);
+  if (e != hipSuccess || n == 0) return hip_status(e);
+  if (!T || !P || !Y) return CHEM_DNN_EINVAL;
+  StepArgs a = step_args(h, n, ld, T, P, Y, nullptr, nullptr, nullptr);
+  a.amax = amax;
+  return hip_status(h->lay.calib(a, grid_for(h, a.ntiles), s));
+}
+
+int32_t chem_dnn_get_scales(chem_dnn *h, float *act_scale, float *w_scale, void *stream) {
+  if (!h || !act_scale || !w_scale) return CHEM_DNN_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  float tmp[FConst::N];
+  hipError_t e = hipMemcpyAsync(tmp, h->fc, sizeof(tmp), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return CHEM_DNN_EHIP;
+  for (int l = 0; l < h->L; ++l) {
+    act_scale[l] = tmp[FConst::ASCALE + l];
+    w_scale[l] = tmp[FConst::WSCALE + l];
+  }
+  return CHEM_DNN_OK;
+}
+
+int32_t chem_dnn_mlp_forward(chem_dnn *h, int64_t B, int64_t ld, const float *x,
+                             const float *params, float *out, float *saved, void *stream) {
+  if (!h || B < 0 || ld < B) return CHEM_DNN_EINVAL;
+  if (B == 0) return CHEM_DNN_OK;
+  if (!x || !params || !out) return CHEM_DNN_EINVAL;
+  if (!saved && B > h->max_batch) return CHEM_DNN_EINVAL;
+  return hip_status(train_mlp_forward(h->widths, B, ld, x, params, out, saved, &h->tr,
+                                      (hipStream_t)stream));
+}
+
+int32_t chem_dnn_mlp_backward(chem_dnn *h, int64_t B, int64_t ld, const float *x,
+                              const float *params, const float *saved, const float *grad_out,
+                              float *grad_params, float *grad_x, void *stream) {
+  if (!h || B < 0 || ld < B) return CHEM_DNN_EINVAL;
+  if (!params || !grad_params) return CHEM_DNN_EINVAL;
+  if (B > 0 && (!x || !grad_out)) return CHEM_DNN_EINVAL;
+  if (B > h->max_batch) return CHEM_DNN_EINVAL;
+  return hip_status(train_mlp_backward(h->widths, B, ld, x, params, saved, grad_out,
+                                       grad_params, grad_x, &h->tr, (hipStream_t)stream));
+}
+
+int32_t chem_dnn_train_step(chem_dnn *h, int64_t B, int64_t ld, const double *T, const double *P,
+                            const double *Y, const float *target, float *params, float *grads,
+                            float *adam_m, float *adam_v, int64_t step, float lr,
+                            int32_t recompute, float *loss, void *stream) {
+  if (!h || B < 1 || ld < B || B > h->max_batch || step < 1) return CHEM_DNN_EINVAL;
+  if (!T || !P || !Y || !target || !params || !grads || !adam_m || !adam_v || !loss)
+    return CHEM_DNN_EINVAL;
+  if (!(lr > 0.0f)) return CHEM_DNN_EINVAL;
+  return hip_status(train_step(h->widths, B, ld, T, P, Y, target, params, grads, adam_m, adam_v,
+                               step, lr, recompute != 0, loss, h->fc, h->dc, &h->tr,
+                               (hipStream_t)stream));
+}
+
+int32_t chem_dnn_destroy(chem_dnn *h) {
+  if (!h) return CHEM_DNN_EINVAL;
+  delete h;
+  return CHEM_DNN_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,145 @@
+// Device-side building blocks of the chemistry-update kernels (gfx950 only).
+//
+// Matrix-core fragment layout used throughout
+// -------------------------------------------
+// Every dense layer is computed transposed, Z^T = W A^T: the weights are the
+// MFMA "A" operand (16 output features x KS input features per instruction
+// group) and the activations are the "B" operand (KS input features x 16
+// cells).  A 16x16 accumulator tile holds, in lane l, cell (l % 16) and output
+// features 4*(l / 16) + r, r = 0..3.
+//
+// A k-step covers KS input features.  In both operands lane l owns a
+// fragment of KS/4 elements; slot j of lane-group g = l / 16 carries input
+// feature
+//        f(q, g, j) = KS*q + 16*(j / 4) + 4*g + (j % 4)
+// (any bijection works as long as both operands use the same one).  With this
+// map the four accumulator values a lane holds for an output row-block are
+// exactly four consecutive slots of the next layer's B fragment of the same
+// lane, so a layer's result is written to LDS by the lane that computed it,
+// without any shuffle, and read back by the next layer as one 16-byte
+// (32-byte for FP8) LDS load per lane.  Weights are packed into the same
+// per-lane fragment order once at initialisation, so each wave streams them
+// from L2 with fully coalesced 1 KiB (2 KiB) loads.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace chemdnn {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef int i4 __attribute__((ext_vector_type(4)));
+typedef int i8v __attribute__((ext_vector_type(8)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+
+// tanh-form GELU, 0.5 x (1 + tanh(v)), v = sqrt(2/pi)(x + 0.044715 x^3),
+// evaluated as x / (1 + 2^(-2 v log2 e)) (the identity 0.5(1 + tanh v) =
+// 1/(1 + e^(-2v))): one exp2 and one reciprocal, no cancellation, and the
+// correct limits 0 and x for large |x|.
+constexpr double kSqrt2OverPi = 0.7978845608028654;
+constexpr double kGeluCubic = 0.044715;
+constexpr float kG1 = (float)(-2.0 * kSqrt2OverPi * 1.4426950408889634);
+constexpr float kG3 = (float)(-2.0 * kSqrt2OverPi * 1.4426950408889634 * kGeluCubic);
+
+__device__ __forceinline__ float gelu(float x) {
+  float p = __builtin_fmaf(x * x, kG3, kG1);
+  float e = __builtin_amdgcn_exp2f(x * p);
+  return x * __builtin_amdgcn_rcpf(1.0f + e);
+}
+
+// Y^lam in FP32 from an FP64 mass fraction, via the exponent split
+// y = m 2^e (m in [1, 2)) so that values far below FLT_MIN keep their
+// magnitude.  Non-positive, NaN or subnormal-double inputs give 0
+// (y^lam < 1e-30 for subnormal doubles).
+__device__ __forceinline__ float ypow(double y, float lam) {
+  if (!(y > 0.0)) return 0.0f;
+  uint64_t bits = __builtin_bit_cast(uint64_t, y);
+  int ef = (int)((bits >> 52) & 0x7ff);
+  if (ef == 0) return 0.0f;
+  if (ef == 0x7ff) return __builtin_inff();
+  double m = __builtin_bit_cast(double, (bits & 0x000fffffffffffffull) | 0x3ff0000000000000ull);
+  float l2 = __builtin_amdgcn_logf((float)m) + (float)(ef - 1023);
+  return __builtin_amdgcn_exp2f(lam * l2);
+}
+
+// ---------------------------------------------------------------- operand formats
+// KS: input features per k-step; FRAG: bytes per lane per fragment;
+// EB: bytes per element; SCALED: operands carry power-of-two scales.
+struct OpF32 {
+  static constexpr int KS = 16, FRAG = 16, EB = 4;
+  static constexpr bool SCALED = false;
+  typedef i4 frag_t;
+  static __device__ __forceinline__ f4 mma(const frag_t &a, const frag_t &b, f4 c) {
+    // bit-cast whole vectors: a bit-cast of a single vector element collapses
+    // every element to the first one in this compiler
+    const f4 af = __builtin_bit_cast(f4, a), bf = __builtin_bit_cast(f4, b);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) c = __builtin_amdgcn_mfma_f32_16x16x4f32(af[r], bf[r], c, 0, 0, 0);
+    return c;
+  }
+  // store 4 values (already scaled) into 4 consecutive slots
+  static __device__ __forceinline__ void store4(uint8_t *p, f4 v) { *(f4 *)p = v; }
+};
+
+struct OpBF16 {
+  static constexpr int KS = 32, FRAG = 16, EB = 2;
+  static constexpr bool SCALED = false;
+  typedef i4 frag_t;
+  static __device__ __forceinline__ f4 mma(const frag_t &a, const frag_t &b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a),
+                                                   __builtin_bit_cast(bf8, b), c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ void store4(uint8_t *p, f4 v) {
+    typedef __bf16 b4 __attribute__((ext_vector_type(4)));
+    b4 o;
+    o[0] = (__bf16)v[0]; o[1] = (__bf16)v[1]; o[2] = (__bf16)v[2]; o[3] = (__bf16)v[3];
+    *(b4 *)p = o;
+  }
+};
+
+struct OpF16 {
+  static constexpr int KS = 32, FRAG = 16, EB = 2;
+  static constexpr bool SCALED = false;
+  typedef i4 frag_t;
+  static __device__ __forceinline__ f4 mma(const frag_t &a, const frag_t &b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8, a),
+                                                  __builtin_bit_cast(h8, b), c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ void store4(uint8_t *p, f4 v) {
+    typedef _Float16 q4 __attribute__((ext_vector_type(4)));
+    q4 o;
+    o[0] = (_Float16)v[0]; o[1] = (_Float16)v[1]; o[2] = (_Float16)v[2]; o[3] = (_Float16)v[3];
+    *(q4 *)p = o;
+  }
+};
+
+// OCP FP8 E4M3 with the K=128 f8f6f4 matrix instruction (unit block scales:
+// the E8M0 scale operand 127 encodes 2^0).  The hardware conversion does not
+// saturate (values past 464 become NaN), so values are clamped to +-448 first.
+struct OpF8 {
+  static constexpr int KS = 128, FRAG = 32, EB = 1;
+  static constexpr bool SCALED = true;
+  typedef i8v frag_t;
+  static __device__ __forceinline__ f4 mma(const frag_t &a, const frag_t &b, f4 c) {
+    return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, c, 0, 0, 0, 127, 0, 127);
+  }
+  static __device__ __forceinline__ uint32_t pack4(f4 v) {
+    float a = __builtin_amdgcn_fmed3f(v[0], -448.0f, 448.0f);
+    float b = __builtin_amdgcn_fmed3f(v[1], -448.0f, 448.0f);
+    float c = __builtin_amdgcn_fmed3f(v[2], -448.0f, 448.0f);
+    float d = __builtin_amdgcn_fmed3f(v[3], -448.0f, 448.0f);
+    uint32_t w = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
+    return __builtin_amdgcn_cvt_pk_fp8_f32(c, d, w, true);
+  }
+  static __device__ __forceinline__ void store4(uint8_t *p, f4 v) { *(uint32_t *)p = pack4(v); }
+};
+
+template <int A, int B> struct Max { static constexpr int v = A > B ? A : B; };
+constexpr int roundup(int x, int m) { return (x + m - 1) / m * m; }
+
+// Input feature held in slot j of lane-group g in k-step q.
+__host__ __device__ constexpr int frag_feature(int KS, int q, int g, int j) {
+  return KS * q + 16 * (j >> 2) + 4 * g + (j & 3);
+}
+
+}  // namespace chemdnn

@@ -1,0 +1,77 @@
+// Host-side structures shared by the C-ABI layer and the kernel translation
+// units.  Not part of the public interface.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace chemdnn {
+
+enum Prec { P_FP32 = 0, P_BF16 = 1, P_FP16 = 2, P_FP8 = 3 };
+
+// Device constants of a handle, FP32 block (indices in floats).
+struct FConst {
+  enum {
+    ZA = 0,        // [32] z = Y^lam * ZA[f] + ZC[f] for species feature f = s + 2
+    ZC = 32,       // [32]
+    PA = 64,       // [32] lam * delta = o * PA[rho] + PB[rho], output row rho = s + 2
+    PB = 96,       // [32]
+    INV_SA = 128,  // [4] 1 / act_scale[l]: multiplier applied before quantising layer l's input
+    SOUT = 132,    // [4] act_scale[l] * w_scale[l]: multiplier of layer l's accumulator
+    WSCALE = 136,  // [4] w_scale[l]
+    ASCALE = 140,  // [4] act_scale[l]
+    LAM = 144,     // lam
+    INV_LAM = 145, // 1 / lam (rounded from FP64)
+    N = 160
+  };
+};
+// FP64 block (indices in doubles).
+struct DConst {
+  enum {
+    T_MU = 0, T_IS = 1, P_MU = 2, P_IS = 3, T_REF = 4, LAM = 5,
+    HF = 8,    // [32] by output row rho = s + 2
+    CP = 40,   // [32]
+    N = 72
+  };
+};
+
+struct StepArgs {
+  const double *T, *P, *Y;
+  double *Y_out, *T_out;
+  uint32_t *n_bad;
+  int64_t n, ld, ntiles;
+  const void *w[4];      // packed weights
+  const float *b[4];     // padded biases (layer 4 shifted by two rows)
+  const float *fc;       // FConst block
+  const double *dc;      // DConst block
+  float *amax;           // calibration output [4] (bit pattern max)
+  int S, thermo;
+};
+
+// Shape and layout of one compiled network configuration.
+struct NetLayout {
+  int KS, FRAG, EB;            // operand format of the hidden layers
+  int MC;                      // cells per tile
+  int R[4], NQ[4];             // row-blocks and k-steps per layer
+  int lds_bytes;
+  // launches
+  hipError_t (*step)(const StepArgs &, int grid, hipStream_t);
+  hipError_t (*calib)(const StepArgs &, int grid, hipStream_t);  // FP32 only, else null
+  hipError_t (*prepare)();     // one-time function attributes
+};
+
+// Finds the compiled configuration for hidden widths (h1, h2, h3) in
+// precision p; returns false when this build has none.
+bool find_layout(int p, int h1, int h2, int h3, NetLayout *out);
+
+// Weight packing (kernels in step.hip).
+hipError_t launch_weight_amax(const float *W, int64_t count, uint32_t *amax_bits, hipStream_t s);
+hipError_t launch_pow2_scales(const uint32_t *amax_bits, float *fc, int nl, int fp8,
+                              hipStream_t s);
+hipError_t launch_pack(const float *W, int N, int K, int rowshift, int R, int NQ, int KS,
+                       int fmt, const float *w_scale, void *dst, hipStream_t s);
+hipError_t launch_pad_bias(const float *b, int N, int rowshift, int NP, float *dst,
+                           hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
+
+}  // namespace chemdnn

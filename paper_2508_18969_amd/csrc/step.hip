@@ -1,0 +1,603 @@
+// Fused, persistent chemistry-update kernel and weight packing (gfx950).
+//
+// One workgroup of four waves (one per SIMD) owns a tile of MC cells at a
+// time and loops over tiles with a grid stride (grid = number of CUs).  Per
+// tile:
+//   pre     FP64 state -> Box-Cox + Z-score (FP32) -> layer-1 B fragments (LDS)
+//   L1+L2   layer 1 is produced in super-chunks of its output rows; each chunk
+//           (bias + GELU + quantise) goes to a double-buffered LDS slot and is
+//           consumed at once as a K-slice of layer 2, whose accumulators stay
+//           in registers: the wide layer-1 activation never exists whole
+//   L3      layer-2 GELU output sits in LDS; layer 3 streams it
+//   L4      layer-3 output reuses that LDS region; linear output layer
+//   post    inverse transform in FP32, update, renormalisation and optional
+//           temperature in FP64, written by the lane that holds the values
+// Waves split every layer's output rows; weights stream from L2 straight
+// into registers with one-k-step-ahead prefetch (each wave reads rows no
+// other wave reads, so weights cross the L2->CU path once per tile).
+#include "common.h"
+#include "internal.h"
+
+namespace chemdnn {
+
+// Split of R output row-blocks x CB cell-blocks over four waves: each wave
+// owns F whole row-blocks (all cell-blocks) plus NREM leftover tiles.
+template <int R, int CB> struct Split {
+  static constexpr int F = R / 4;
+  static constexpr int RR = R % 4;
+  static constexpr int NREM = RR * CB / 4;
+  static constexpr int T = F * CB + NREM;
+  static_assert((RR * CB) % 4 == 0, "row-blocks must split evenly over four waves");
+  static __device__ __forceinline__ int rem_rb(int w, int k) { return 4 * F + (w * NREM + k) / CB; }
+  static __device__ __forceinline__ int rem_cb(int w, int k) { return (w * NREM + k) % CB; }
+};
+
+constexpr int padH(int h, int ks, int cb) {
+  int g = ks > 16 ? ks : 16;
+  int p = roundup(h, g);
+  while ((((p / 16) % 4) * cb) % 4) p += g;
+  return p;
+}
+
+template <class Op_, int CB_, int H1_, int H2_, int H3_> struct Cfg {
+  using Op = Op_;
+  using frag_t = typename Op::frag_t;
+  static constexpr int KS = Op::KS, FRAG = Op::FRAG, EB = Op::EB, CB = CB_, MC = 16 * CB_;
+  static constexpr int NQ1 = (32 + KS - 1) / KS;    // layer-1 k-steps (inputs <= 32)
+  static constexpr int SC = KS > 64 ? KS : 64;      // layer-1 rows per super-chunk
+  static constexpr int H1P = roundup(H1_, SC);
+  static constexpr int H2P = padH(H2_, KS, CB_);
+  static constexpr int H3P = padH(H3_, KS, CB_);
+  static constexpr int R1 = H1P / 16, R2 = H2P / 16, R3 = H3P / 16, R4 = 2;
+  static constexpr int NQ2 = H1P / KS, NQ3 = H2P / KS, NQ4 = H3P / KS;
+  static constexpr int NSC = H1P / SC, RB1W = SC / 64, QSC = SC / KS, RPQ = KS / 16;
+  using S2 = Split<R2, CB_>;
+  using S3 = Split<R3, CB_>;
+  static constexpr int QBYTES = CB * 64 * FRAG;     // one k-step of a tile's activations
+  static constexpr int LDS_A0 = 0;
+  static constexpr int LDS_A1 = LDS_A0 + NQ1 * QBYTES;
+  static constexpr int LDS_A2 = LDS_A1 + 2 * QSC * QBYTES;
+  static constexpr int LDS_BYTES = LDS_A2 + Max<NQ3, NQ4>::v * QBYTES;
+  static_assert(LDS_BYTES <= 160 * 1024, "LDS budget");
+};
+
+template <class frag_t>
+__device__ __forceinline__ frag_t ldg_frag(const uint8_t *base, int idx, int lane) {
+  return *(const frag_t *)(base + ((size_t)idx * 64 + lane) * sizeof(frag_t));
+}
+template <class frag_t>
+__device__ __forceinline__ frag_t lds_frag(const uint8_t *base, int idx, int lane) {
+  return *(const frag_t *)(base + ((size_t)idx * 64 + lane) * sizeof(frag_t));
+}
+
+__device__ __forceinline__ float umaxf(float a, float b) { return a > b ? a : b; }
+
+template <class C, bool CALIB>
+__global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
+  using Op = typename C::Op;
+  using frag_t = typename C::frag_t;
+  using S2 = typename C::S2;
+  using S3 = typename C::S3;
+  constexpr int CB = C::CB, KS = C::KS, FRAG = C::FRAG, EB = C::EB, RPQ = C::RPQ;
+  extern __shared__ __align__(16) uint8_t smem[];
+  uint8_t *const A0 = smem + C::LDS_A0;
+  uint8_t *const A1 = smem + C::LDS_A1;
+  uint8_t *const A2 = smem + C::LDS_A2;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, cl = lane & 15;
+  const float *fc = a.fc;
+  const double *dc = a.dc;
+  const uint8_t *W1 = (const uint8_t *)a.w[0], *W2 = (const uint8_t *)a.w[1];
+  const uint8_t *W3 = (const uint8_t *)a.w[2], *W4 = (const uint8_t *)a.w[3];
+  const float lam = fc[FConst::LAM], inv_lam = fc[FConst::INV_LAM];
+  float inv_sa[4], sout[4];
+#pragma unroll
+  for (int l = 0; l < 4; ++l) {
+    inv_sa[l] = Op::SCALED ? fc[FConst::INV_SA + l] : 1.0f;
+    sout[l] = Op::SCALED ? fc[FConst::SOUT + l] : 1.0f;
+  }
+  float amx[4] = {0.f, 0.f, 0.f, 0.f};
+
+  for (int64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+    const int64_t cell0 = tile * C::MC;
+
+    // ------------------------------------------------------------ preprocess
+    // Lane (cell 16w + cl, group g) computes input features f = 16h + 4g + r.
+    if (w < CB) {
+      const int64_t i = cell0 + 16 * w + cl;
+      const bool valid = i < a.n;
+      f4 v[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int f = 16 * h + 4 * g + r;
+          float z = 0.0f;
+          if (valid) {
+            if (f == 0)
+              z = (float)((a.T[i] - dc[DConst::T_MU]) * dc[DConst::T_IS]);
+            else if (f == 1)
+              z = (float)((a.P[i] - dc[DConst::P_MU]) * dc[DConst::P_IS]);
+            else if (f - 2 < a.S)
+              z = __builtin_fmaf(ypow(a.Y[(int64_t)(f - 2) * a.ld + i], lam), fc[FConst::ZA + f],
+                                 fc[FConst::ZC + f]);
+          }
+          if (CALIB) amx[0] = umaxf(amx[0], __builtin_fabsf(z));
+          v[h][r] = z * inv_sa[0];
+        }
+      if constexpr (KS == 16) {
+        // two k-steps of 16: feature 16h + 4g + r sits in k-step h, slot r
+        Op::store4(A0 + ((0 * CB + w) * 64 + lane) * FRAG, v[0]);
+        Op::store4(A0 + ((1 * CB + w) * 64 + lane) * FRAG, v[1]);
+      } else {
+        uint8_t *p = A0 + (w * 64 + lane) * FRAG;
+        Op::store4(p, v[0]);
+        Op::store4(p + 4 * EB, v[1]);
+        // slots 8.. (features >= 32) are zero padding
+#pragma unroll
+        for (int o = 8 * EB; o < FRAG; o += 4) *(uint32_t *)(p + o) = 0u;
+      }
+    }
+    __syncthreads();
+
+    frag_t a0[C::NQ1][CB];
+#pragma unroll
+    for (int q = 0; q < C::NQ1; ++q)
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) a0[q][cb] = lds_frag<frag_t>(A0, q * CB + cb, lane);
+
+    // Layer 1, super-chunk sc, into A1 buffer `buf`.
+    auto layer1 = [&](int sc, int buf) {
+#pragma unroll
+      for (int ii = 0; ii < C::RB1W; ++ii) {
+        const int rbl = w * C::RB1W + ii;              // row-block within the chunk
+        const int rb = sc * (C::SC / 16) + rbl;
+        frag_t wf[C::NQ1];
+#pragma unroll
+        for (int q = 0; q < C::NQ1; ++q) wf[q] = ldg_frag<frag_t>(W1, rb * C::NQ1 + q, lane);
+        const f4 bias = *(const f4 *)(a.b[0] + 16 * rb + 4 * g);
+        uint8_t *dst = A1 + buf * C::QSC * C::QBYTES;
+        const int q2l = rbl / RPQ, j0 = 4 * (rbl % RPQ);
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+          f4 acc = Op::SCALED ? f4{0.f, 0.f, 0.f, 0.f} : bias;
+#pragma unroll
+          for (int q = 0; q < C::NQ1; ++q) acc = Op::mma(wf[q], a0[q][cb], acc);
+          f4 y;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            float zz = Op::SCALED ? __builtin_fmaf(acc[r], sout[0], bias[r]) : acc[r];
+            y[r] = gelu(zz);
+          }
+          if (CALIB && cell0 + 16 * cb + cl < a.n)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) amx[1] = umaxf(amx[1], __builtin_fabsf(y[r]));
+          if (Op::SCALED) y *= inv_sa[1];
+          Op::store4(dst + ((q2l * CB + cb) * 64 + lane) * FRAG + j0 * EB, y);
+        }
+      }
+    };
+
+    // ------------------------------------------------------------ layers 1+2
+    f4 acc2[S2::T];
+#pragma unroll
+    for (int i = 0; i < S2::F; ++i) {
+      const f4 bias = Op::SCALED ? f4{0.f, 0.f, 0.f, 0.f}
+                                 : *(const f4 *)(a.b[1] + 16 * (w * S2::F + i) + 4 * g);
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) acc2[i * CB + cb] = bias;
+    }
+#pragma unroll
+    for (int k = 0; k < S2::NREM; ++k)
+      acc2[S2::F * CB + k] = Op::SCALED ? f4{0.f, 0.f, 0.f, 0.f}
+                                        : *(const f4 *)(a.b[1] + 16 * S2::rem_rb(w, k) + 4 * g);
+
+    layer1(0, 0);
+    __syncthreads();
+    constexpr int NW2 = S2::F + S2::NREM;
+    frag_t wc[NW2];
+#pragma unroll
+    for (int i = 0; i < S2::F; ++i) wc[i] = ldg_frag<frag_t>(W2, (w * S2::F + i) * C::NQ2, lane);
+#pragma unroll
+    for (int k = 0; k < S2::NREM; ++k)
+      wc[S2::F + k] = ldg_frag<frag_t>(W2, S2::rem_rb(w, k) * C::NQ2, lane);
+
+    for (int sc = 0; sc < C::NSC; ++sc) {
+      // next chunk of layer 1 (the last iteration recomputes chunk 0 into the
+      // idle buffer, which keeps the loop body branch-free)
+      const int nsc = (sc + 1 == C::NSC) ? 0 : sc + 1;
+      layer1(nsc, (sc + 1) & 1);
+      const uint8_t *src = A1 + (sc & 1) * C::QSC * C::QBYTES;
+#pragma unroll
+      for (int ql = 0; ql < C::QSC; ++ql) {
+        const int q = sc * C::QSC + ql;
+        const int qn = (q + 1 < C::NQ2) ? q + 1 : q;
+        frag_t wn[NW2];
+#pragma unroll
+        for (int i = 0; i < S2::F; ++i) wn[i] = ldg_frag<frag_t>(W2, (w * S2::F + i) * C::NQ2 + qn, lane);
+#pragma unroll
+        for (int k = 0; k < S2::NREM; ++k)
+          wn[S2::F + k] = ldg_frag<frag_t>(W2, S2::rem_rb(w, k) * C::NQ2 + qn, lane);
+        frag_t af[CB];
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) af[cb] = lds_frag<frag_t>(src, ql * CB + cb, lane);
+#pragma unroll
+        for (int i = 0; i < S2::F; ++i)
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb) acc2[i * CB + cb] = Op::mma(wc[i], af[cb], acc2[i * CB + cb]);
+#pragma unroll
+        for (int k = 0; k < S2::NREM; ++k) {
+          const frag_t ar = lds_frag<frag_t>(src, ql * CB + S2::rem_cb(w, k), lane);
+          acc2[S2::F * CB + k] = Op::mma(wc[S2::F + k], ar, acc2[S2::F * CB + k]);
+        }
+#pragma unroll
+        for (int i = 0; i < NW2; ++i) wc[i] = wn[i];
+      }
+      __syncthreads();
+    }
+
+    // layer-2 activation -> LDS (layer-3 B fragments)
+    auto put = [&](uint8_t *base, int rb, int cb, f4 y) {
+      Op::store4(base + (((rb / RPQ) * CB + cb) * 64 + lane) * FRAG + 4 * (rb % RPQ) * EB, y);
+    };
+    {
+#pragma unroll
+      for (int t = 0; t < S2::T; ++t) {
+        const int rb = t < S2::F * CB ? w * S2::F + t / CB : S2::rem_rb(w, t - S2::F * CB);
+        const int cb = t < S2::F * CB ? t % CB : S2::rem_cb(w, t - S2::F * CB);
+        f4 bias = Op::SCALED ? *(const f4 *)(a.b[1] + 16 * rb + 4 * g) : f4{0.f, 0.f, 0.f, 0.f};
+        f4 y;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          y[r] = gelu(Op::SCALED ? __builtin_fmaf(acc2[t][r], sout[1], bias[r]) : acc2[t][r]);
+        if (CALIB && cell0 + 16 * cb + cl < a.n)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) amx[2] = umaxf(amx[2], __builtin_fabsf(y[r]));
+        if (Op::SCALED) y *= inv_sa[2];
+        put(A2, rb, cb, y);
+      }
+    }
+    __syncthreads();
+
+    // ------------------------------------------------------------ layer 3
+    f4 acc3[S3::T];
+#pragma unroll
+    for (int i = 0; i < S3::F; ++i) {
+      const f4 bias = Op::SCALED ? f4{0.f, 0.f, 0.f, 0.f}
+                                 : *(const f4 *)(a.b[2] + 16 * (w * S3::F + i) + 4 * g);
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) acc3[i * CB + cb] = bias;
+    }
+#pragma unroll
+    for (int k = 0; k < S3::NREM; ++k)
+      acc3[S3::F * CB + k] = Op::SCALED ? f4{0.f, 0.f, 0.f, 0.f}
+                                        : *(const f4 *)(a.b[2] + 16 * S3::rem_rb(w, k) + 4 * g);
+    {
+      constexpr int NW3 = S3::F + S3::NREM;
+      frag_t wc3[NW3];
+#pragma unroll
+      for (int i = 0; i < S3::F; ++i) wc3[i] = ldg_frag<frag_t>(W3, (w * S3::F + i) * C::NQ3, lane);
+#pragma unroll
+      for (int k = 0; k < S3::NREM; ++k)
+        wc3[S3::F + k] = ldg_frag<frag_t>(W3, S3::rem_rb(w, k) * C::NQ3, lane);
+      for (int q = 0; q < C::NQ3; ++q) {
+        const int qn = (q + 1 < C::NQ3) ? q + 1 : q;
+        frag_t wn[NW3];
+#pragma unroll
+        for (int i = 0; i < S3::F; ++i) wn[i] = ldg_frag<frag_t>(W3, (w * S3::F + i) * C::NQ3 + qn, lane);
+#pragma unroll
+        for (int k = 0; k < S3::NREM; ++k)
+          wn[S3::F + k] = ldg_frag<frag_t>(W3, S3::rem_rb(w, k) * C::NQ3 + qn, lane);
+        frag_t af[CB];
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) af[cb] = lds_frag<frag_t>(A2, q * CB + cb, lane);
+#pragma unroll
+        for (int i = 0; i < S3::F; ++i)
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb) acc3[i * CB + cb] = Op::mma(wc3[i], af[cb], acc3[i * CB + cb]);
+#pragma unroll
+        for (int k = 0; k < S3::NREM; ++k) {
+          const frag_t ar = lds_frag<frag_t>(A2, q * CB + S3::rem_cb(w, k), lane);
+          acc3[S3::F * CB + k] = Op::mma(wc3[S3::F + k], ar, acc3[S3::F * CB + k]);
+        }
+#pragma unroll
+        for (int i = 0; i < NW3; ++i) wc3[i] = wn[i];
+      }
+    }
+    __syncthreads();  // every wave is done reading the layer-2 activation
+    {
+#pragma unroll
+      for (int t = 0; t < S3::T; ++t) {
+        const int rb = t < S3::F * CB ? w * S3::F + t / CB : S3::rem_rb(w, t - S3::F * CB);
+        const int cb = t < S3::F * CB ? t % CB : S3::rem_cb(w, t - S3::F * CB);
+        f4 bias = Op::SCALED ? *(const f4 *)(a.b[2] + 16 * rb + 4 * g) : f4{0.f, 0.f, 0.f, 0.f};
+        f4 y;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          y[r] = gelu(Op::SCALED ? __builtin_fmaf(acc3[t][r], sout[2], bias[r]) : acc3[t][r]);
+        if (CALIB && cell0 + 16 * cb + cl < a.n)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) amx[3] = umaxf(amx[3], __builtin_fabsf(y[r]));
+        if (Op::SCALED) y *= inv_sa[3];
+        put(A2, rb, cb, y);
+      }
+    }
+    __syncthreads();
+    if (CALIB) continue;
+
+    // ------------------------------------------------------------ layer 4 + post
+    if (w < CB) {
+      f4 o[2];
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+        o[rb] = Op::SCALED ? f4{0.f, 0.f, 0.f, 0.f} : *(const f4 *)(a.b[3] + 16 * rb + 4 * g);
+      for (int q = 0; q < C::NQ4; ++q) {
+        const frag_t af = lds_frag<frag_t>(A2, q * CB + w, lane);
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb) o[rb] = Op::mma(ldg_frag<frag_t>(W4, rb * C::NQ4 + q, lane), af, o[rb]);
+      }
+      if (Op::SCALED)
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb) {
+          const f4 bias = *(const f4 *)(a.b[3] + 16 * rb + 4 * g);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) o[rb][r] = __builtin_fmaf(o[rb][r], sout[3], bias[r]);
+        }
+
+      // post: lane holds output rows rho = 16h + 4g + r, species s = rho - 2
+      const int64_t i = cell0 + 16 * w + cl;
+      const bool valid = i < a.n;
+      const int64_t ic = valid ? i : 0;
+      const double T = a.T[ic], P = a.P[ic];
+      bool bad = !__builtin_isfinite(T) || !__builtin_isfinite(P);
+      double Y[8], Yh[8];
+      double ssum = 0.0, h0 = 0.0;
+      const double t_ref = dc[DConst::T_REF];
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int rho = 16 * h + 4 * g + r, s = rho - 2, j = 4 * h + r;
+          Y[j] = 0.0;
+          Yh[j] = 0.0;
+          if (s >= 0 && s < a.S) {
+            const double y = a.Y[(int64_t)s * a.ld + ic];
+            Y[j] = y;
+            bad |= !__builtin_isfinite(y);
+            const float b = ypow(y, lam);
+            const float wv = __builtin_fmaf(o[h][r], fc[FConst::PA + rho], fc[FConst::PB + rho]);
+            double dy;
+            if (b > 0.0f && __builtin_fabsf(wv) <= 0.5f * b) {
+              // Y* - Y = Y ((1 + wv/b)^(1/lam) - 1), no cancellation for small steps
+              const float em1 = expm1f(log1pf(wv / b) * inv_lam);
+              dy = y * (double)em1;
+            } else {
+              // Y* = (Y^lam + lam delta)^(1/lam), clamped at 0
+              const float base = b + wv;
+              const double ystar =
+                  base > 0.0f ? (double)__builtin_amdgcn_exp2f(__builtin_amdgcn_logf(base) * inv_lam) : 0.0;
+              dy = ystar - y;
+            }
+            double yh = y + dy;
+            yh = yh > 0.0 ? yh : 0.0;
+            Yh[j] = yh;
+            ssum += yh;
+            if (a.thermo) h0 += y * (dc[DConst::HF + rho] + dc[DConst::CP + rho] * (T - t_ref));
+          }
+        }
+      // the cell's four lanes: l, l^16, l^32, l^48
+      ssum += __shfl_xor(ssum, 16);
+      ssum += __shfl_xor(ssum, 32);
+      int badi = bad ? 1 : 0;
+      badi |= __shfl_xor(badi, 16);
+      badi |= __shfl_xor(badi, 32);
+      double Yn[8];
+      double hn = 0.0, cn = 0.0;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        Yn[j] = Yh[j] / ssum;
+        const int rho = 16 * (j >> 2) + 4 * g + (j & 3);
+        if (a.thermo && rho >= 2 && rho - 2 < a.S) {
+          hn += Yn[j] * dc[DConst::HF + rho];
+          cn += Yn[j] * dc[DConst::CP + rho];
+        }
+      }
+      double Tn = T;
+      if (a.thermo) {
+        h0 += __shfl_xor(h0, 16);
+        h0 += __shfl_xor(h0, 32);
+        hn += __shfl_xor(hn, 16);
+        hn += __shfl_xor(hn, 32);
+        cn += __shfl_xor(cn, 16);
+        cn += __shfl_xor(cn, 32);
+        Tn = t_ref + (h0 - hn) / cn;
+      }
+      bool okc = !badi && ssum > 0.0 && __builtin_isfinite(ssum) && __builtin_isfinite(Tn);
+      int fin = 1;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) fin &= __builtin_isfinite(Yn[j]) ? 1 : 0;
+      fin &= __shfl_xor(fin, 16);
+      fin &= __shfl_xor(fin, 32);
+      okc = okc && fin;
+      if (valid) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int s = 16 * h + 4 * g + r - 2, j = 4 * h + r;
+            if (s >= 0 && s < a.S) a.Y_out[(int64_t)s * a.ld + i] = okc ? Yn[j] : Y[j];
+          }
+        if (g == 0) {
+          if (a.T_out) a.T_out[i] = okc ? Tn : T;
+          if (!okc && a.n_bad) atomicAdd(a.n_bad, 1u);
+        }
+      }
+    }
+  }
+
+  if (CALIB) {
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      float m = amx[l];
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) m = umaxf(m, __shfl_xor(m, o));
+      if (lane == 0) atomicMax((unsigned int *)(a.amax + l), __builtin_bit_cast(unsigned int, m));
+    }
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+template <class C>
+static hipError_t launch_step(const StepArgs &a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL((chem_step_kernel<C, false>), dim3(grid), dim3(256), C::LDS_BYTES, s, a);
+  return hipGetLastError();
+}
+template <class C>
+static hipError_t launch_calib(const StepArgs &a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL((chem_step_kernel<C, true>), dim3(grid), dim3(256), C::LDS_BYTES, s, a);
+  return hipGetLastError();
+}
+template <class C, bool WITH_CALIB>
+static hipError_t prepare() {
+  hipError_t e = hipFuncSetAttribute((const void *)chem_step_kernel<C, false>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, C::LDS_BYTES);
+  if (e == hipSuccess && WITH_CALIB)
+    e = hipFuncSetAttribute((const void *)chem_step_kernel<C, true>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, C::LDS_BYTES);
+  return e;
+}
+
+template <class C, bool WITH_CALIB>
+static void fill_layout(NetLayout *L) {
+  L->KS = C::KS;
+  L->FRAG = C::FRAG;
+  L->EB = C::EB;
+  L->MC = C::MC;
+  L->R[0] = C::R1; L->R[1] = C::R2; L->R[2] = C::R3; L->R[3] = C::R4;
+  L->NQ[0] = C::NQ1; L->NQ[1] = C::NQ2; L->NQ[2] = C::NQ3; L->NQ[3] = C::NQ4;
+  L->lds_bytes = C::LDS_BYTES;
+  L->step = launch_step<C>;
+  L->calib = WITH_CALIB ? launch_calib<C> : nullptr;
+  L->prepare = prepare<C, WITH_CALIB>;
+}
+
+// Compiled network shapes: the 17-species net (400, 200, 100) and the
+// 29-species net (1600, 800, 400).
+bool find_layout(int p, int h1, int h2, int h3, NetLayout *out) {
+#define CHEM_SHAPE(H1, H2, H3)                                                        \
+  if (h1 == H1 && h2 == H2 && h3 == H3) {                                             \
+    switch (p) {                                                                      \
+      case P_FP32: fill_layout<Cfg<OpF32, 2, H1, H2, H3>, true>(out); return true;    \
+      case P_BF16: fill_layout<Cfg<OpBF16, 4, H1, H2, H3>, false>(out); return true;  \
+      case P_FP16: fill_layout<Cfg<OpF16, 4, H1, H2, H3>, false>(out); return true;   \
+      default: return false;                                                          \
+    }                                                                                 \
+  }
+  CHEM_SHAPE(400, 200, 100)
+  CHEM_SHAPE(1600, 800, 400)
+#undef CHEM_SHAPE
+  return false;
+}
+
+// ------------------------------------------------------------------ packing
+__global__ void weight_amax_kernel(const float *W, int64_t count, uint32_t *amax_bits) {
+  float m = 0.0f;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    m = umaxf(m, __builtin_fabsf(W[i]));
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) m = umaxf(m, __shfl_xor(m, o));
+  if ((threadIdx.x & 63) == 0) atomicMax(amax_bits, __builtin_bit_cast(uint32_t, m));
+}
+
+// Weight scales: the smallest power of two s with amax / s <= 448 (FP8),
+// computed in FP64; 1 for the other formats.  Also forms the accumulator
+// multipliers act_scale * w_scale.  Writes into the FConst block.
+__global__ void pow2_scale_kernel(const uint32_t *amax_bits, float *fc, int nl, int fp8) {
+  int l = threadIdx.x;
+  if (l >= nl) return;
+  float s = 1.0f;
+  if (fp8) {
+    double amax = (double)__builtin_bit_cast(float, amax_bits[l]);
+    if (amax > 0.0) {
+      int e;
+      double m = frexp(amax / 448.0, &e);
+      int k = (m == 0.5) ? e - 1 : e;
+      s = (float)ldexp(1.0, k);
+    }
+  }
+  fc[FConst::WSCALE + l] = s;
+  fc[FConst::SOUT + l] = fc[FConst::ASCALE + l] * s;
+}
+
+// Packs W [N][K] (row-major FP32) into fragment order: fragment (rb, q) of
+// lane l, slot j holds W[16 rb + l%16 - rowshift][frag_feature(q, l/16, j)] / s,
+// zero outside the matrix.  fmt: 0 FP32, 1 BF16, 2 FP16, 3 FP8 E4M3.
+__global__ void pack_kernel(const float *W, int N, int K, int rowshift, int R, int NQ, int KS,
+                            int fmt, const float *w_scale, uint8_t *dst) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;   // (rb, q, lane)
+  if (t >= (int64_t)R * NQ * 64) return;
+  const int lane = (int)(t % 64);
+  const int q = (int)((t / 64) % NQ);
+  const int rb = (int)(t / (64 * (int64_t)NQ));
+  const int row = 16 * rb + (lane & 15) - rowshift;
+  const float inv = fmt == 3 ? 1.0f / *w_scale : 1.0f;
+  const int ne = KS / 4;
+  for (int j = 0; j < ne; ++j) {
+    const int k = frag_feature(KS, q, lane >> 4, j);
+    float v = (row >= 0 && row < N && k < K) ? W[(int64_t)row * K + k] * inv : 0.0f;
+    const int64_t e = t * ne + j;
+    switch (fmt) {
+      case 0: ((float *)dst)[e] = v; break;
+      case 1: ((__bf16 *)dst)[e] = (__bf16)v; break;
+      case 2: ((_Float16 *)dst)[e] = (_Float16)v; break;
+      default: {
+        float c = __builtin_amdgcn_fmed3f(v, -448.0f, 448.0f);
+        dst[e] = (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(c, 0.0f, 0, false) & 0xff);
+      }
+    }
+  }
+}
+
+__global__ void pad_bias_kernel(const float *b, int N, int rowshift, int NP, float *dst) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= NP) return;
+  int r = i - rowshift;
+  dst[i] = (r >= 0 && r < N) ? b[r] : 0.0f;
+}
+
+__global__ void fill_u32_kernel(uint32_t *p, uint32_t v, int64_t n) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+hipError_t launch_weight_amax(const float *W, int64_t count, uint32_t *amax_bits, hipStream_t s) {
+  int blocks = (int)((count + 255) / 256);
+  if (blocks > 1024) blocks = 1024;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(weight_amax_kernel, dim3(blocks), dim3(256), 0, s, W, count, amax_bits);
+  return hipGetLastError();
+}
+hipError_t launch_pow2_scales(const uint32_t *amax_bits, float *fc, int nl, int fp8,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(pow2_scale_kernel, dim3(1), dim3(64), 0, s, amax_bits, fc, nl, fp8);
+  return hipGetLastError();
+}
+hipError_t launch_pack(const float *W, int N, int K, int rowshift, int R, int NQ, int KS, int fmt,
+                       const float *w_scale, void *dst, hipStream_t s) {
+  int64_t threads = (int64_t)R * NQ * 64;
+  hipLaunchKernelGGL(pack_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, W, N,
+                     K, rowshift, R, NQ, KS, fmt, w_scale, (uint8_t *)dst);
+  return hipGetLastError();
+}
+hipError_t launch_pad_bias(const float *b, int N, int rowshift, int NP, float *dst, hipStream_t s) {
+  hipLaunchKernelGGL(pad_bias_kernel, dim3((NP + 255) / 256), dim3(256), 0, s, b, N, rowshift, NP,
+                     dst);
+  return hipGetLastError();
+}
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+}  // namespace chemdnn

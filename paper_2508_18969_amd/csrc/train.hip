@@ -1,0 +1,408 @@
+// Training kernels (FP32): a strided MFMA GEMM with fused epilogues,
+// deterministic split-K weight gradients, MSE loss and Adam.
+//
+// Forward  z_l = W_l a_(l-1) + b_l, a_l = GELU(z_l) (GELU is applied inside
+//          the next GEMM's operand loader, so only z_l is stored);
+// backward dW_l = dZ_l a_(l-1)^T (split over the batch, partials summed in a
+//          fixed order), db_l = row sums of dZ_l, dZ_(l-1) = (W_l^T dZ_l) *
+//          GELU'(z_(l-1)) fused in the GEMM epilogue.  No floating-point
+//          atomics anywhere, so gradients are bitwise reproducible.
+#include "common.h"
+#include "internal.h"
+#include "train.h"
+
+namespace chemdnn {
+
+namespace {
+
+constexpr int kMaxSplit = 32;
+constexpr int kSplitChunk = 2048;
+
+// d/dx of the tanh-form GELU with s = 0.5 (1 + tanh v) = 1/(1 + e^(-2v)):
+// GELU' = s + x * 2 s (1 - s) * sqrt(2/pi) (1 + 3 * 0.044715 x^2).
+__device__ __forceinline__ float gelu_grad(float x) {
+  float p = __builtin_fmaf(x * x, kG3, kG1);
+  float s = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(x * p));
+  float dv = (float)kSqrt2OverPi * __builtin_fmaf(3.0f * (float)kGeluCubic, x * x, 1.0f);
+  return __builtin_fmaf(x * 2.0f * s * (1.0f - s), dv, s);
+}
+
+enum { EPI_FWD = 0, EPI_DA = 1, EPI_PART = 2 };
+
+struct GemmArgs {
+  const float *A, *B;
+  float *C;
+  int64_t sam, sak, sbk, sbn, scm, scn;
+  int M, N;
+  int64_t K, kchunk;
+  int gelu_b;              // apply GELU to B operand values on load
+  const float *bias;       // EPI_FWD: [M]
+  const float *zprev;      // EPI_DA: multiply by GELU'(zprev[m * scm + n * scn]) if set
+  int64_t part_stride;     // EPI_PART: offset of split z's partial block
+};
+
+// C = A B over one K-split; 64x64 output tile, four waves of 32x32, the
+// 16x16x4 FP32 matrix instruction.
+template <int EPI>
+__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
+  __shared__ float As[16][65], Bs[16][65];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wm = w >> 1, wn = w & 1;
+  const int64_t m0 = (int64_t)blockIdx.y * 64, n0 = (int64_t)blockIdx.x * 64;
+  const int64_t k0 = (int64_t)blockIdx.z * g.kchunk;
+  const int64_t k1 = (k0 + g.kchunk < g.K) ? k0 + g.kchunk : g.K;
+  f4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+  const bool a_kfast = g.sak == 1, b_nfast = g.sbn == 1;
+  for (int64_t kb = k0; kb < k1; kb += 16) {
+#pragma unroll
+    for (int e0 = 0; e0 < 1024; e0 += 256) {
+      const int e = e0 + tid;
+      int m, k;
+      if (a_kfast) { m = e >> 4; k = e & 15; } else { m = e & 63; k = e >> 6; }
+      const int64_t gm = m0 + m, gk = kb + k;
+      As[k][m] = (gm < g.M && gk < k1) ? g.A[gm * g.sam + gk * g.sak] : 0.0f;
+    }
+#pragma unroll
+    for (int e0 = 0; e0 < 1024; e0 += 256) {
+      const int e = e0 + tid;
+      int n, k;
+      if (b_nfast) { k = e >> 6; n = e & 63; } else { n = e >> 4; k = e & 15; }
+      const int64_t gn = n0 + n, gk = kb + k;
+      float v = (gn < g.N && gk < k1) ? g.B[gk * g.sbk + gn * g.sbn] : 0.0f;
+      Bs[k][n] = g.gelu_b ? gelu(v) : v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k4 = 0; k4 < 4; ++k4) {
+      const int kk = 4 * k4 + (lane >> 4);
+      const float a0 = As[kk][wm * 32 + (lane & 15)], a1 = As[kk][wm * 32 + 16 + (lane & 15)];
+      const float b0 = Bs[kk][wn * 32 + (lane & 15)], b1 = Bs[kk][wn * 32 + 16 + (lane & 15)];
+      acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  float *C = g.C + (EPI == EPI_PART ? blockIdx.z * g.part_stride : 0);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t m = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + r;
+        const int64_t n = n0 + wn * 32 + j * 16 + (lane & 15);
+        if (m < g.M && n < g.N) {
+          float v = acc[i][j][r];
+          const int64_t o = m * g.scm + n * g.scn;
+          if (EPI == EPI_FWD) v += g.bias[m];
+          if (EPI == EPI_DA && g.zprev) v *= gelu_grad(g.zprev[o]);
+          C[o] = v;
+        }
+      }
+}
+
+// out[i] = sum over z of part[z * stride + i], z in increasing order.
+__global__ void reduce_parts_kernel(const float *part, int64_t stride, int nz, int64_t n,
+                                    float *out) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float s = 0.0f;
+  for (int z = 0; z < nz; ++z) s += part[z * stride + i];
+  out[i] = s;
+}
+
+// out[m] = sum_b dz[m * ld + b]: one workgroup per row, fixed-order tree.
+__global__ void rowsum_kernel(const float *dz, int64_t ld, int64_t B, float *out) {
+  __shared__ float red[256];
+  const int64_t m = blockIdx.x;
+  float s = 0.0f;
+  for (int64_t b = threadIdx.x; b < B; b += 256) s += dz[m * ld + b];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[m] = red[0];
+}
+
+// dO = 2 (o - t) / (B S); per-block partial sums of (o - t)^2.
+__global__ void mse_kernel(const float *o, int64_t ldo, const float *t, int64_t ldt, int S,
+                           int64_t B, float *dO, float *lpart) {
+  __shared__ float red[256];
+  const int64_t n = (int64_t)S * B;
+  const float inv = 2.0f / (float)((double)B * S);
+  float s = 0.0f;
+  for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+    const int64_t sp = e / B, b = e % B;
+    const float d = o[sp * ldo + b] - t[sp * ldt + b];
+    dO[sp * ldo + b] = d * inv;
+    s = __builtin_fmaf(d, d, s);
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) lpart[blockIdx.x] = red[0];
+}
+
+__global__ void loss_final_kernel(const float *lpart, int nb, double denom, float *loss) {
+  if (threadIdx.x != 0) return;
+  double s = 0.0;
+  for (int i = 0; i < nb; ++i) s += (double)lpart[i];
+  *loss = (float)(s / denom);
+}
+
+// Normalised network input from the FP64 state, the same arithmetic as the
+// inference kernel's preprocessing.
+__global__ void features_kernel(const double *T, const double *P, const double *Y, int64_t ld,
+                                int64_t B, int S, const float *fc, const double *dc, float *x,
+                                int64_t ldx) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= B) return;
+  const float lam = fc[FConst::LAM];
+  x[i] = (float)((T[i] - dc[DConst::T_MU]) * dc[DConst::T_IS]);
+  x[ldx + i] = (float)((P[i] - dc[DConst::P_MU]) * dc[DConst::P_IS]);
+  for (int s = 0; s < S; ++s)
+    x[(int64_t)(s + 2) * ldx + i] =
+        __builtin_fmaf(ypow(Y[(int64_t)s * ld + i], lam), fc[FConst::ZA + s + 2], fc[FConst::ZC + s + 2]);
+}
+
+__global__ void adam_kernel(float *p, const float *g, float *m, float *v, int64_t n, float lr,
+                            float c1, float c2) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = 0.9f * m[i] + 0.1f * gi;
+  const float vi = 0.999f * v[i] + 0.001f * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi * c1) / (__builtin_sqrtf(vi * c2) + 1e-8f);
+}
+
+unsigned blocks_for(int64_t n, int per = 256) { return (unsigned)((n + per - 1) / per); }
+
+hipError_t gemm(int epi, const GemmArgs &g, int nsplit, hipStream_t s) {
+  dim3 grid(blocks_for(g.N, 64), blocks_for(g.M, 64), nsplit);
+  switch (epi) {
+    case EPI_FWD: hipLaunchKernelGGL(gemm_kernel<EPI_FWD>, grid, dim3(256), 0, s, g); break;
+    case EPI_DA: hipLaunchKernelGGL(gemm_kernel<EPI_DA>, grid, dim3(256), 0, s, g); break;
+    default: hipLaunchKernelGGL(gemm_kernel<EPI_PART>, grid, dim3(256), 0, s, g); break;
+  }
+  return hipGetLastError();
+}
+
+size_t param_off(const int *w, int l) {
+  size_t o = 0;
+  for (int i = 0; i < l; ++i) o += (size_t)w[i] * w[i + 1] + w[i + 1];
+  return o;
+}
+
+int split_count(int64_t B) {
+  int64_t n = (B + kSplitChunk - 1) / kSplitChunk;
+  return (int)(n > kMaxSplit ? kMaxSplit : (n < 1 ? 1 : n));
+}
+
+int64_t max_layer_weights(const int *w) {
+  int64_t m = 0;
+  for (int l = 0; l < 4; ++l) m = m > (int64_t)w[l] * w[l + 1] ? m : (int64_t)w[l] * w[l + 1];
+  return m;
+}
+
+// Forward of the 4-layer net.  z: pre-activations [H1+H2+H3][ldz]; out [S][ldo].
+hipError_t forward(const int *w, int64_t B, const float *x, int64_t ldx, const float *params,
+                   float *z, int64_t ldz, float *out, int64_t ldo, hipStream_t s) {
+  int64_t zoff = 0;
+  const float *in = x;
+  int64_t ldin = ldx;
+  int gelu_in = 0;
+  for (int l = 0; l < 4; ++l) {
+    const int N = w[l + 1], K = w[l];
+    GemmArgs g{};
+    g.A = params + param_off(w, l);
+    g.sam = K; g.sak = 1;
+    g.B = in; g.sbk = ldin; g.sbn = 1;
+    g.gelu_b = gelu_in;
+    float *dst = (l < 3) ? z + zoff * ldz : out;
+    const int64_t ldd = (l < 3) ? ldz : ldo;
+    g.C = dst; g.scm = ldd; g.scn = 1;
+    g.M = N; g.N = (int)B; g.K = K; g.kchunk = K;
+    g.bias = params + param_off(w, l) + (size_t)N * K;
+    hipError_t e = gemm(EPI_FWD, g, 1, s);
+    if (e != hipSuccess) return e;
+    in = dst;
+    ldin = ldd;
+    gelu_in = 1;
+    zoff += (l < 3) ? N : 0;
+  }
+  return hipSuccess;
+}
+
+// Backward given dL/d out (gout [S][ldg]) and the pre-activations z.
+hipError_t backward(const int *w, int64_t B, const float *x, int64_t ldx, const float *params,
+                    const float *z, int64_t ldz, const float *gout, int64_t ldg, float *gparams,
+                    float *gx, int64_t ldgx, TrainScratch *t, hipStream_t s) {
+  int64_t zoffs[4] = {0, w[1], (int64_t)w[1] + w[2], 0};
+  const float *dZ = gout;
+  int64_t lddz = ldg;
+  const int nsplit = split_count(B);
+  const int64_t kchunk = ((B + nsplit - 1) / nsplit + 15) / 16 * 16;
+  int pp = 0;
+  for (int l = 3; l >= 0; --l) {
+    const int N = w[l + 1], K = w[l];
+    const float *ain = (l == 0) ? x : z + zoffs[l - 1] * ldz;
+    const int64_t ldain = (l == 0) ? ldx : ldz;
+    // dW_l = dZ_l a_(l-1)^T over the batch, split in fixed chunks
+    GemmArgs g{};
+    g.A = dZ; g.sam = lddz; g.sak = 1;
+    g.B = ain; g.sbk = 1; g.sbn = ldain;
+    g.gelu_b = (l > 0);
+    g.C = t->part; g.scm = K; g.scn = 1;
+    g.M = N; g.N = K; g.K = B; g.kchunk = kchunk;
+    g.part_stride = (int64_t)N * K;
+    hipError_t e = gemm(EPI_PART, g, nsplit, s);
+    if (e != hipSuccess) return e;
+    float *gW = gparams + param_off(w, l);
+    hipLaunchKernelGGL(reduce_parts_kernel, dim3(blocks_for((int64_t)N * K)), dim3(256), 0, s,
+                       (const float *)t->part, (int64_t)N * K, nsplit, (int64_t)N * K, gW);
+    hipLaunchKernelGGL(rowsum_kernel, dim3(N), dim3(256), 0, s, dZ, lddz, B, gW + (size_t)N * K);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // dZ_(l-1) = (W_l^T dZ_l) * GELU'(z_(l-1)), or grad_x for l = 0
+    if (l > 0 || gx) {
+      GemmArgs d{};
+      d.A = params + param_off(w, l); d.sam = 1; d.sak = K;    // W^T: (k, n) -> W[n][k]
+      d.B = dZ; d.sbk = lddz; d.sbn = 1;
+      float *dst = (l > 0) ? t->dz[pp] : gx;
+      const int64_t ldd = (l > 0) ? t->cap : ldgx;
+      d.C = dst; d.scm = ldd; d.scn = 1;
+      d.M = K; d.N = (int)B; d.K = N; d.kchunk = N;
+      d.zprev = (l > 0) ? z + zoffs[l - 1] * ldz : nullptr;
+      if (l > 0 && ldz != ldd) return hipErrorInvalidValue;   // epilogue indexes z like C
+      e = gemm(EPI_DA, d, 1, s);
+      if (e != hipSuccess) return e;
+      dZ = dst;
+      lddz = ldd;
+      pp ^= 1;
+    }
+  }
+  return hipSuccess;
+}
+
+}  // namespace
+
+size_t train_scratch_bytes(const int *w, int64_t cap) {
+  if (cap <= 0) return 0;
+  const int64_t H = (int64_t)w[1] + w[2] + w[3];
+  int64_t mx = w[4];
+  for (int l = 1; l < 4; ++l) mx = mx > w[l] ? mx : w[l];
+  size_t f = (size_t)cap * (w[0] + H + w[4] + 2 * mx) + (size_t)kMaxSplit * max_layer_weights(w) +
+             1024;
+  return f * sizeof(float) + 8 * 256;
+}
+
+void train_scratch_layout(TrainScratch *t, uint8_t *base, const int *w, int64_t cap) {
+  *t = TrainScratch{};
+  t->cap = cap;
+  if (cap <= 0) return;
+  const int64_t H = (int64_t)w[1] + w[2] + w[3];
+  int64_t mx = w[4];
+  for (int l = 1; l < 4; ++l) mx = mx > w[l] ? mx : w[l];
+  auto take = [&](size_t floats) {
+    float *p = (float *)base;
+    base += (floats * sizeof(float) + 255) / 256 * 256;
+    return p;
+  };
+  t->x = take((size_t)cap * w[0]);
+  t->z = take((size_t)cap * H);
+  t->out = take((size_t)cap * w[4]);
+  t->dz[0] = take((size_t)cap * mx);
+  t->dz[1] = take((size_t)cap * mx);
+  t->part = take((size_t)kMaxSplit * max_layer_weights(w));
+  t->lpart = take(1024);
+  t->act = nullptr;
+  t->nsplit = kMaxSplit;
+}
+
+hipError_t train_prepare() { return hipSuccess; }
+
+hipError_t train_mlp_forward(const int *w, int64_t B, int64_t ld, const float *x,
+                             const float *params, float *out, float *saved, TrainScratch *t,
+                             hipStream_t s) {
+  if (saved) return forward(w, B, x, ld, params, saved, ld, out, ld, s);
+  if (B > t->cap) return hipErrorInvalidValue;
+  return forward(w, B, x, ld, params, t->z, t->cap, out, ld, s);
+}
+
+hipError_t train_mlp_backward(const int *w, int64_t B, int64_t ld, const float *x,
+                              const float *params, const float *saved, const float *grad_out,
+                              float *grad_params, float *grad_x, TrainScratch *t, hipStream_t s) {
+  if (B > t->cap) return hipErrorInvalidValue;
+  const float *z = saved;
+  int64_t ldz = ld;
+  if (!z) {
+    hipError_t e = forward(w, B, x, ld, params, t->z, t->cap, t->out, t->cap, s);
+    if (e != hipSuccess) return e;
+    z = t->z;
+    ldz = t->cap;
+  }
+  if (ldz != t->cap) {
+    // the fused GELU' epilogue reads z with the scratch leading dimension
+    for (int l = 0; l < 3; ++l) {
+      int64_t off = 0;
+      for (int i = 0; i < l; ++i) off += w[i + 1];
+      hipError_t e = hipMemcpy2DAsync(t->z + off * t->cap, t->cap * sizeof(float),
+                                      z + off * ldz, ldz * sizeof(float), B * sizeof(float),
+                                      w[l + 1], hipMemcpyDeviceToDevice, s);
+      if (e != hipSuccess) return e;
+    }
+    z = t->z;
+    ldz = t->cap;
+  }
+  return backward(w, B, x, ld, params, z, ldz, grad_out, ld, grad_params, grad_x, ld, t, s);
+}
+
+hipError_t train_step(const int *w, int64_t B, int64_t ld, const double *T, const double *P,
+                      const double *Y, const float *target, float *params, float *grads,
+                      float *adam_m, float *adam_v, int64_t step, float lr, bool recompute,
+                      float *loss, const float *fc, const double *dc, TrainScratch *t,
+                      hipStream_t s) {
+  if (B > t->cap) return hipErrorInvalidValue;
+  const int S = w[4];
+  hipLaunchKernelGGL(features_kernel, dim3(blocks_for(B)), dim3(256), 0, s, T, P, Y, ld, B, S, fc,
+                     dc, t->x, t->cap);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = forward(w, B, t->x, t->cap, params, t->z, t->cap, t->out, t->cap, s);
+  if (e != hipSuccess) return e;
+  // dL/do into dz[1] (the backward ping-pong starts writing dz[0])
+  int nb = (int)blocks_for((int64_t)S * B);
+  if (nb > 1024) nb = 1024;
+  hipLaunchKernelGGL(mse_kernel, dim3(nb), dim3(256), 0, s, (const float *)t->out, t->cap, target,
+                     ld, S, B, t->dz[1], t->lpart);
+  hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(64), 0, s, (const float *)t->lpart, nb,
+                     (double)B * S, loss);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (recompute) {
+    // keep only the inputs: regenerate the pre-activations for the backward
+    e = forward(w, B, t->x, t->cap, params, t->z, t->cap, t->out, t->cap, s);
+    if (e != hipSuccess) return e;
+  }
+  // mse_kernel wrote dO with the output's leading dimension (cap)
+  e = backward(w, B, t->x, t->cap, params, t->z, t->cap, t->dz[1], t->cap, grads, nullptr, 0, t, s);
+  if (e != hipSuccess) return e;
+  const int64_t np = (int64_t)param_off(w, 4);
+  const double c1 = 1.0 / (1.0 - pow(0.9, (double)step));
+  const double c2 = 1.0 / (1.0 - pow(0.999, (double)step));
+  hipLaunchKernelGGL(adam_kernel, dim3(blocks_for(np)), dim3(256), 0, s, params, (const float *)grads,
+                     adam_m, adam_v, np, lr, (float)c1, (float)c2);
+  return hipGetLastError();
+}
+
+}  // namespace chemdnn

@@ -1,0 +1,89 @@
+"""The C ABI without a GPU: the library loads, exports every symbol the header
+declares, and rejects bad arguments before touching a device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "chem_dnn.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2508_18969_amd import binding
+    if not os.path.exists(binding.LIB):
+        pytest.skip("library not built")
+    return binding
+
+
+def test_header_declares_what_the_library_exports(L):
+    decl = set(re.findall(r"\b(chem_dnn_[a-z_]+)\s*\(", open(HEADER).read()))
+    assert decl == set(L.EXPORTS)
+    lib = L.lib()
+    for name in decl:
+        assert hasattr(lib, name), name
+    assert lib.chem_dnn_abi_version() == 1
+    for st in (0, -1, -2, -3, -4, -5):
+        assert L.strerror(st) and L.strerror(st) != "unknown status"
+
+
+def _desc(L, **kw):
+    net = synth.make_net(1)
+    args = dict(widths=net.widths, precision="fp32", in_mean=net.in_mean, in_std=net.in_std)
+    args.update(kw)
+    return L.make_desc(**args)
+
+
+def test_workspace_bytes_and_validation(L):
+    d, keep = _desc(L)
+    n = L.workspace_bytes(d)
+    assert n > 4 * 110017          # at least the packed FP32 weights
+    d2, k2 = _desc(L, max_batch=65536)
+    assert L.workspace_bytes(d2) > n + 65536 * 700 * 4
+    bad = [dict(widths=(19, 400, 200, 100, 16)),           # S mismatch
+           dict(widths=(19, 400, 200, 17)),                # 3 layers: unsupported
+           dict(widths=(19, 0, 200, 100, 17)),
+           dict(precision=7),
+           dict(in_std=np.zeros(19)),
+           dict(precision="fp8")]                          # FP8 needs act_amax
+    for kw in bad:
+        d3, k3 = _desc(L, **kw)
+        with pytest.raises(L.ChemDNNError) as e:
+            L.workspace_bytes(d3)
+        assert e.value.status in (L.EINVAL, L.EUNSUPPORTED)
+    d4, k4 = _desc(L, widths=(19, 64, 64, 64, 17))          # valid but not compiled
+    with pytest.raises(L.ChemDNNError) as e:
+        L.workspace_bytes(d4)
+    assert e.value.status == L.EUNSUPPORTED
+
+
+def test_entry_points_reject_null_handles(L):
+    lib = L.lib()
+    assert lib.chem_dnn_step(None, 10, 10, None, None, None, None, None, None, None) == L.EINVAL
+    assert lib.chem_dnn_destroy(None) == L.EINVAL
+    assert lib.chem_dnn_set_params(None, None, None) == L.EINVAL
+    assert lib.chem_dnn_train_step(None, 1, 1, None, None, None, None, None, None, None, None, 1,
+                                   C.c_float(1e-3), 0, None, None) == L.EINVAL
+    d, keep = _desc(L)
+    out = C.c_void_p()
+    # no workspace: caught before any device call
+    assert lib.chem_dnn_init(C.byref(d), C.c_void_p(1), None, 0, None, C.byref(out)) == L.EWORKSPACE
+    assert lib.chem_dnn_workspace_bytes(C.byref(d), None) == L.EINVAL
+
+
+def test_init_without_device_reports_enodev(L):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a device is present")
+    d, keep = _desc(L)
+    n = L.workspace_bytes(d)
+    buf = (C.c_uint8 * (n + 256))()
+    addr = (C.addressof(buf) + 255) // 256 * 256
+    out = C.c_void_p()
+    st = L.lib().chem_dnn_init(C.byref(d), C.c_void_p(16), C.c_void_p(addr), n, None, C.byref(out))
+    assert st == L.ENODEV and not out.value

@@ -1,0 +1,182 @@
+"""GPU parity of the chemistry update (chem_dnn_step through the C ABI)
+against the FP64 oracle on seeded inputs."""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import chem
+from tests.helpers import dev_state, make_handle, rel_err
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _run(h, st, ld=None):
+    T, P, Y = dev_state(st, ld=ld)
+    nbad = torch.zeros(1, dtype=torch.int32, device="cuda")
+    Yn, Tn = h.step(T, P, Y, n_bad=nbad)
+    torch.cuda.synchronize()
+    return Yn.cpu().numpy(), (Tn.cpu().numpy() if Tn is not None else None), int(nbad.item())
+
+
+# ------------------------------------------------------------------ FP32 paths vs FP64
+@pytest.mark.parametrize("n", [4096, 4096 - 37, 1, 33])
+def test_small_net_fp32_matches_fp64_oracle(n):
+    """17-species net, FP32 operands: Y_new within 1e-5 relative (floor 1e-10)
+    and T_new within 1e-5 relative of the FP64 oracle; several tiles and a
+    ragged tail."""
+    _note(f"case small fp32 n={n}")
+    net = synth.make_net(1)
+    thermo = synth.make_thermo(1, 17)
+    st = synth.make_state(1, n)
+    h = make_handle(net, "fp32", thermo=thermo)
+    Yg, Tg, nbad = _run(h, st)
+    ref = chem.step(st.T, st.P, st.Y, net, thermo=thermo)
+    assert nbad == 0
+    e_y = rel_err(Yg, ref["Y_new"])
+    e_t = rel_err(Tg, ref["T_new"], floor=1.0)
+    _note(f"  rel err Y {e_y:.3e}  T {e_t:.3e}")
+    assert e_y <= 1e-5
+    assert e_t <= 1e-5
+    np.testing.assert_allclose(Yg.sum(axis=0), 1.0, atol=1e-13)
+
+
+def test_large_net_fp32_matches_fp64_oracle():
+    _note("case large fp32 n=2048+5")
+    net = synth.make_net(2)
+    thermo = synth.make_thermo(2, 29)
+    st = synth.make_state(2, 2048 + 5)
+    h = make_handle(net, "fp32", thermo=thermo)
+    Yg, Tg, _ = _run(h, st)
+    ref = chem.step(st.T, st.P, st.Y, net, thermo=thermo)
+    e_y = rel_err(Yg, ref["Y_new"])
+    e_t = rel_err(Tg, ref["T_new"], floor=1.0)
+    _note(f"  rel err Y {e_y:.3e}  T {e_t:.3e}")
+    assert e_y <= 1e-5
+    assert e_t <= 1e-5
+
+
+# ------------------------------------------------------------------ narrow formats
+def _rel(a, b, floor=1e-10):
+    return np.abs(a - b) / np.maximum(np.abs(b), floor)
+
+
+@pytest.mark.parametrize("prec,fmt", [("bf16", "bf16"), ("fp16", "f16")])
+def test_large_net_narrow_matches_emulation(prec, fmt):
+    """29-species net with bf16 / fp16 operands against the oracle that rounds
+    the same operands (FP64 arithmetic otherwise).
+
+    The two sides round activations that differ by FP32 accumulation error, so
+    an activation near a rounding boundary can land one narrow-format ulp apart
+    (a "flip"); each flip moves a cell's output by a fraction of one ulp.  The
+    bar: the GPU's deviation from the emulation is a small fraction of the
+    quantisation error itself (emulation vs exact FP64) in RMS, median, 99th
+    percentile and maximum.  The error against exact FP64 is printed."""
+    _note(f"case large {prec} n=4096+11")
+    net = synth.make_net(2)
+    thermo = synth.make_thermo(2, 29)
+    st = synth.make_state(2, 4096 + 11)
+    h = make_handle(net, prec, thermo=thermo)
+    Yg, Tg, _ = _run(h, st)
+    emu = chem.step(st.T, st.P, st.Y, net, fmt=fmt, thermo=thermo)
+    ex = chem.step(st.T, st.P, st.Y, net, thermo=thermo)
+    ge, ee = Yg - emu["Y_new"], emu["Y_new"] - ex["Y_new"]
+    rg, re = _rel(Yg, emu["Y_new"]), _rel(emu["Y_new"], ex["Y_new"])
+    rms_g, rms_e = np.sqrt(np.mean(ge ** 2)), np.sqrt(np.mean(ee ** 2))
+    _note(f"  gpu-emu: rms {rms_g:.2e} med {np.median(rg):.2e} p99 {np.quantile(rg, .99):.2e} "
+          f"max {rg.max():.2e} T {np.abs(Tg - emu['T_new']).max():.2e} | "
+          f"emu-fp64: rms {rms_e:.2e} med {np.median(re):.2e} p99 {np.quantile(re, .99):.2e} "
+          f"max {re.max():.2e} | gpu-fp64 max abs dY {np.abs(Yg - ex['Y_new']).max():.2e} "
+          f"T {np.abs(Tg - ex['T_new']).max():.2e} K")
+    assert rms_g <= 0.25 * rms_e
+    assert np.median(rg) <= 0.05 * np.median(re)
+    assert np.quantile(rg, 0.99) <= 0.5 * np.quantile(re, 0.99)
+    assert rg.max() <= 0.5 * re.max()
+    tg, te = Tg - emu["T_new"], emu["T_new"] - ex["T_new"]
+    assert np.sqrt(np.mean(tg ** 2)) <= 0.25 * np.sqrt(np.mean(te ** 2))
+    assert np.abs(tg).max() <= np.abs(te).max()
+
+
+# ------------------------------------------------------------------ properties
+def test_cells_are_independent_and_runs_deterministic():
+    _note("case independence bf16")
+    net = synth.make_net(2)
+    st = synth.make_state(2, 300)
+    h = make_handle(net, "bf16")
+    Y1, _, _ = _run(h, st)
+    Y2, _, _ = _run(h, st)
+    assert np.array_equal(Y1, Y2)
+    one = synth.State(st.T[17:18].copy(), st.P[17:18].copy(), st.Y[:, 17:18].copy())
+    Yo, _, _ = _run(h, one)
+    assert np.array_equal(Yo[:, 0], Y1[:, 17])
+
+
+def test_padded_leading_dimension_and_in_place():
+    _note("case ld/in-place fp32 small")
+    net = synth.make_net(1)
+    st = synth.make_state(1, 200)
+    h = make_handle(net, "fp32")
+    Yref, _, _ = _run(h, st)
+    T, P, Y = dev_state(st, ld=256)
+    assert Y.stride(0) == 256
+    h.step(T, P, Y, Y_out=Y)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(Y.cpu().numpy(), Yref)
+
+
+def test_bad_cells_pass_through():
+    _note("case bad cells")
+    net = synth.make_net(1)
+    thermo = synth.make_thermo(1, 17)
+    st = synth.make_state(1, 64)
+    st.T[3] = np.nan
+    st.Y[5, 9] = np.inf
+    st.P[20] = -np.inf
+    h = make_handle(net, "fp32", thermo=thermo)
+    Yg, Tg, nbad = _run(h, st)
+    assert nbad == 3
+    for c in (3, 9, 20):
+        np.testing.assert_array_equal(Yg[:, c], st.Y[:, c])
+    assert np.isnan(Tg[3])
+    ref = chem.step(st.T, st.P, st.Y, net, thermo=thermo)
+    good = ~ref["bad"]
+    assert rel_err(Yg[:, good], ref["Y_new"][:, good]) <= 1e-5
+
+
+def test_zero_and_tiny_mass_fractions():
+    """Y = 0 and Y far below FLT_MIN take the exponent-split path."""
+    _note("case tiny Y")
+    net = synth.make_net(1)
+    st = synth.make_state(1, 128)
+    st.Y[0, :32] = 0.0
+    st.Y[1, 32:64] = 1e-300
+    st.Y[2, 64:96] = 1e-45
+    st.Y /= st.Y.sum(axis=0)
+    h = make_handle(net, "fp32")
+    Yg, _, nbad = _run(h, st)
+    ref = chem.step(st.T, st.P, st.Y, net)
+    assert nbad == 0
+    assert rel_err(Yg, ref["Y_new"]) <= 1e-5
+
+
+def test_empty_batch_is_noop():
+    net = synth.make_net(1)
+    h = make_handle(net, "fp32")
+    T = torch.zeros(0, dtype=torch.float64, device="cuda")
+    Y = torch.zeros((17, 0), dtype=torch.float64, device="cuda")
+    h.step(T, T, Y)
+    torch.cuda.synchronize()

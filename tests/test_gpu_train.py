@@ -1,0 +1,147 @@
+"""GPU parity of the training path (chem_dnn_mlp_forward / _mlp_backward /
+_train_step and the autograd Function) against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import chem, train
+from tests.helpers import dev_state, make_handle
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+WIDTHS = synth.NET_SMALL
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _tensor_rel(got, ref):
+    return float(np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-30))
+
+
+def _per_tensor(g, widths):
+    W, b = train.unflatten(g, widths)
+    return W + b
+
+
+def _setup(B, seed=0):
+    net = synth.make_net(4)
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal((WIDTHS[0], B))
+    t = 0.5 * rng.standard_normal((WIDTHS[-1], B))
+    return net, x, t
+
+
+@pytest.mark.parametrize("B", [4096, 1000])
+def test_forward_backward_match_fp64(B):
+    print(f"case train fwd/bwd B={B}", flush=True)
+    net, x, t = _setup(B)
+    h = make_handle(net, "fp32", max_batch=B)
+    p = torch.tensor(net.flat_params(), device="cuda")
+    xd = torch.tensor(x, dtype=torch.float32, device="cuda")
+    saved = torch.empty((sum(WIDTHS[1:-1]), B), dtype=torch.float32, device="cuda")
+    out = h.mlp_forward(xd, p, saved)
+    p64 = net.flat_params().astype(np.float64)
+    x32 = x.astype(np.float32).astype(np.float64)
+    o_ref, zs = train.forward(x32, p64, WIDTHS)
+    np.testing.assert_allclose(out.cpu().numpy(), o_ref, rtol=1e-4, atol=1e-5)
+    _, go = train.mse(o_ref, t)
+    god = torch.tensor(go, dtype=torch.float32, device="cuda")
+    gp, gx = h.mlp_backward(xd, p, saved, god, want_grad_x=True)
+    g_ref, gx_ref = train.backward(x32, p64, WIDTHS, zs, go.astype(np.float32).astype(np.float64))
+    torch.cuda.synchronize()
+    gpn = gp.cpu().numpy().astype(np.float64)
+    for a, r in zip(_per_tensor(gpn, WIDTHS), _per_tensor(g_ref, WIDTHS)):
+        assert _tensor_rel(a, r) <= 1e-4
+    assert _tensor_rel(gx.cpu().numpy(), gx_ref) <= 1e-4
+    # recomputation of the pre-activations gives bitwise the same gradient
+    gp2, _ = h.mlp_backward(xd, p, None, god)
+    gp3, _ = h.mlp_backward(xd, p, saved, god)
+    torch.cuda.synchronize()
+    assert torch.equal(gp2, gp) and torch.equal(gp3, gp)
+
+
+def test_train_step_matches_fp64_and_is_reproducible():
+    B = 2048 + 7
+    print(f"case train_step B={B}", flush=True)
+    net = synth.make_net(4)
+    st = synth.make_state(4, B)
+    rng = np.random.default_rng(3)
+    tgt = 0.3 * rng.standard_normal((17, B))
+    h = make_handle(net, "fp32", max_batch=4096)
+    T, P, Y = dev_state(st)
+    td = torch.tensor(tgt, dtype=torch.float32, device="cuda")
+    res = []
+    for recompute in (False, True):
+        p = torch.tensor(net.flat_params(), device="cuda")
+        m = torch.zeros_like(p)
+        v = torch.zeros_like(p)
+        g = torch.empty_like(p)
+        losses = []
+        for k in (1, 2, 3):
+            loss = h.train_step(T, P, Y, td, p, g, m, v, k, lr=1e-3, recompute=recompute)
+            losses.append(float(loss.item()))
+        torch.cuda.synchronize()
+        res.append((p.cpu().numpy(), g.cpu().numpy(), losses))
+    assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1])
+    # oracle: features in FP64 from the same statistics, three Adam steps
+    x = chem.features(st.T, st.P, st.Y, net.in_mean, net.in_std, net.lam)
+    q = net.flat_params().astype(np.float64)
+    mm = np.zeros_like(q)
+    vv = np.zeros_like(q)
+    for k in (1, 2, 3):
+        r = train.train_step(x, tgt.astype(np.float32).astype(np.float64), q, mm, vv, k, WIDTHS)
+        assert abs(r["loss"] - res[0][2][k - 1]) <= 1e-5 * r["loss"]
+        last_g = r["grads"]
+        q, mm, vv = r["params"], r["m"], r["v"]
+    for a, b in zip(_per_tensor(res[0][1].astype(np.float64), WIDTHS), _per_tensor(last_g, WIDTHS)):
+        assert _tensor_rel(a, b) <= 1e-3
+    # Adam moves every parameter by about lr per step whatever |g| is, so a
+    # gradient at rounding level may flip one step; nearly all agree closely
+    d = np.abs(res[0][0] - q)
+    assert np.mean(d > 1e-5) < 1e-3 and d.max() <= 6.1e-3
+
+
+def test_autograd_function_matches_finite_differences():
+    print("case autograd", flush=True)
+    from paper_2508_18969_amd import autograd_function
+    F = autograd_function()
+    net, x, t = _setup(512, seed=5)
+    h = make_handle(net, "fp32", max_batch=512)
+    p = torch.tensor(net.flat_params(), device="cuda", requires_grad=True)
+    xd = torch.tensor(x, dtype=torch.float32, device="cuda", requires_grad=True)
+    td = torch.tensor(t, dtype=torch.float32, device="cuda")
+    for recompute in (False, True):
+        out = F.apply(xd, p, h, recompute)
+        loss = ((out - td) ** 2).mean()
+        gp, gx = torch.autograd.grad(loss, (p, xd))
+        p64 = net.flat_params().astype(np.float64)
+        o, zs = train.forward(x.astype(np.float32).astype(np.float64), p64, WIDTHS)
+        _, go = train.mse(o, t)
+        g_ref, gx_ref = train.backward(x.astype(np.float32).astype(np.float64), p64, WIDTHS, zs, go)
+        assert _tensor_rel(gp.cpu().numpy(), g_ref) <= 1e-4
+        assert _tensor_rel(gx.cpu().numpy(), gx_ref) <= 1e-4
+    # directional finite difference through the GPU forward
+    d = torch.randn_like(p) * 1e-3
+    with torch.no_grad():
+        lp = ((F.apply(xd, p + d, h, False) - td) ** 2).mean().double()
+        lm = ((F.apply(xd, p - d, h, False) - td) ** 2).mean().double()
+    fd = float((lp - lm) / 2)
+    an = float((gp.double() * d.double()).sum())
+    assert abs(fd - an) <= 1e-2 * abs(an) + 1e-9
+
+
+def test_calibration_amax_matches_oracle():
+    print("case calibrate", flush=True)
+    for cfg in (1, 2):
+        net = synth.make_net(cfg)
+        st = synth.make_state(cfg, 3000, stream="calibration")
+        h = make_handle(net, "fp32")
+        T, P, Y = dev_state(st)
+        am = h.calibrate(T, P, Y).cpu().numpy().astype(np.float64)
+        ref = chem.layer_input_amax(st.T, st.P, st.Y, net)
+        np.testing.assert_allclose(am, ref, rtol=2e-5)
