@@ -54,20 +54,63 @@ template <class Op_, int CB_, int H1_, int H2_, int H3_> struct Cfg {
   using S2 = Split<R2, CB_>;
   using S3 = Split<R3, CB_>;
   static constexpr int QBYTES = CB * 64 * FRAG;     // one k-step of a tile's activations
-  static constexpr int LDS_A0 = 0;
+  static constexpr int NW1 = RB1W * NQ1;             // layer-1 fragments per wave per chunk
+  static constexpr int NBIAS = H1P + H2P + H3P + 32; // biases of all layers, FP32
+  static constexpr int LDS_BIAS = 0;
+  static constexpr int LDS_A0 = roundup(NBIAS * 4, 256);
   static constexpr int LDS_A1 = LDS_A0 + NQ1 * QBYTES;
-  static constexpr int LDS_A2 = LDS_A1 + 2 * QSC * QBYTES;
-  static constexpr int LDS_BYTES = LDS_A2 + Max<NQ3, NQ4>::v * QBYTES;
+  static constexpr int LDS_W1 = LDS_A1 + 2 * QSC * QBYTES;  // two-slot per-wave layer-1 ring
+  static constexpr int LDS_A2 = LDS_W1 + 2 * 4 * NW1 * 64 * FRAG;
+  // layer-2 weights stream through a two-slot per-wave LDS ring that lives in
+  // the region which later holds the layer-2 activation
+  static constexpr int NW2 = S2::F + S2::NREM;               // fragments per wave per k-step
+  static constexpr int RING_SLOT = NW2 * 64 * FRAG;            // one wave, one k-step
+  static constexpr int RING_BYTES = 2 * 4 * RING_SLOT;
+  static constexpr int A2_BYTES = Max<NQ3, NQ4>::v * QBYTES;
+  static constexpr int LDS_BYTES = LDS_A2 + Max<A2_BYTES, RING_BYTES>::v;
   static_assert(LDS_BYTES <= 160 * 1024, "LDS budget");
 };
 
+// One wave copies fragment block `idx` (64 lanes x FRAG bytes) from global
+// memory straight into LDS at `dst` (wave-uniform), bypassing registers.
+// Addresses are formed as a wave-uniform block base plus a 32-bit lane
+// offset, so the loads use a scalar base register and one shared offset VGPR.
+template <int FRAG>
+__device__ __forceinline__ void dma_frag(const uint8_t *base, int idx, int lane, uint8_t *dst) {
+  static_assert(FRAG == 16 || FRAG == 32, "fragment size");
+  const uint8_t *blk = base + (size_t)idx * (64 * FRAG);
+#pragma unroll
+  for (int h = 0; h < FRAG / 16; ++h)
+    __builtin_amdgcn_global_load_lds(
+        (const __attribute__((address_space(1))) void *)(blk + (uint32_t)(lane * FRAG + h * 16)),
+        (__attribute__((address_space(3))) void *)(dst + h * 64 * 16), 16, 0, 0);
+}
+// Waits until at most N vector-memory operations of this wave are in flight.
+// Direct-to-LDS copies are not tracked by the compiler's own wait insertion;
+// the memory clobber keeps LDS reads from moving above the wait.
+// vmcnt is a 6-bit counter: a larger bound is replaced by 63, which waits
+// for more copies than needed and is therefore still safe.
+constexpr int cap63(int n) { return n > 63 ? 63 : n; }
+template <int N>
+__device__ __forceinline__ void wait_vmem() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+
+// Workgroup barrier for LDS traffic only: unlike __syncthreads it does not
+// wait for outstanding global loads, so weight copies stay in flight.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 template <class frag_t>
 __device__ __forceinline__ frag_t ldg_frag(const uint8_t *base, int idx, int lane) {
-  return *(const frag_t *)(base + ((size_t)idx * 64 + lane) * sizeof(frag_t));
+  const uint8_t *blk = base + (size_t)idx * (64 * sizeof(frag_t));
+  return *(const frag_t *)(blk + (uint32_t)(lane * sizeof(frag_t)));
 }
 template <class frag_t>
 __device__ __forceinline__ frag_t lds_frag(const uint8_t *base, int idx, int lane) {
-  return *(const frag_t *)(base + ((size_t)idx * 64 + lane) * sizeof(frag_t));
+  return *(const frag_t *)(base + (idx * 64 + lane) * (int)sizeof(frag_t));
 }
 
 __device__ __forceinline__ float umaxf(float a, float b) { return a > b ? a : b; }
@@ -83,11 +126,14 @@ __global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
   uint8_t *const A0 = smem + C::LDS_A0;
   uint8_t *const A1 = smem + C::LDS_A1;
   uint8_t *const A2 = smem + C::LDS_A2;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, cl = lane & 15;
+  // the wave index is uniform: keeping it scalar lets every weight address be a
+  // scalar base plus one per-lane offset
+  const int lane = threadIdx.x & 63, g = lane >> 4, cl = lane & 15;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const float *fc = a.fc;
   const double *dc = a.dc;
-  const uint8_t *W1 = (const uint8_t *)a.w[0], *W2 = (const uint8_t *)a.w[1];
-  const uint8_t *W3 = (const uint8_t *)a.w[2], *W4 = (const uint8_t *)a.w[3];
+  const uint8_t *const W1g = (const uint8_t *)a.w[0], *const W2g = (const uint8_t *)a.w[1];
+  const uint8_t *const W3g = (const uint8_t *)a.w[2], *const W4g = (const uint8_t *)a.w[3];
   const float lam = fc[FConst::LAM], inv_lam = fc[FConst::INV_LAM];
   float inv_sa[4], sout[4];
 #pragma unroll
@@ -97,8 +143,24 @@ __global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
   }
   float amx[4] = {0.f, 0.f, 0.f, 0.f};
 
+  // all biases live in LDS for the whole kernel: no global loads in the
+  // weight-streaming loops besides the direct-to-LDS copies
+  float *const Bl = (float *)(smem + C::LDS_BIAS);
+  for (int i = threadIdx.x; i < C::NBIAS; i += blockDim.x) {
+    const int l = i < C::H1P ? 0 : i < C::H1P + C::H2P ? 1 : i < C::H1P + C::H2P + C::H3P ? 2 : 3;
+    const int o = l == 0 ? 0 : l == 1 ? C::H1P : l == 2 ? C::H1P + C::H2P : C::H1P + C::H2P + C::H3P;
+    Bl[i] = a.b[l][i - o];
+  }
+  const float *const B1 = Bl, *const B2 = Bl + C::H1P, *const B3 = Bl + C::H1P + C::H2P;
+  const float *const B4 = Bl + C::H1P + C::H2P + C::H3P;
+  __syncthreads();
+
   for (int64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
     const int64_t cell0 = tile * C::MC;
+    // Opaque copies of the weight bases: address arithmetic is redone per tile
+    // instead of being hoisted out of the tile loop and kept live (spilled).
+    const uint8_t *W1 = W1g, *W2 = W2g, *W3 = W3g, *W4 = W4g;
+    asm volatile("" : "+s"(W1), "+s"(W2), "+s"(W3), "+s"(W4));
 
     // ------------------------------------------------------------ preprocess
     // Lane (cell 16w + cl, group g) computes input features f = 16h + 4g + r.
@@ -145,16 +207,17 @@ __global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
 #pragma unroll
       for (int cb = 0; cb < CB; ++cb) a0[q][cb] = lds_frag<frag_t>(A0, q * CB + cb, lane);
 
-    // Layer 1, super-chunk sc, into A1 buffer `buf`.
-    auto layer1 = [&](int sc, int buf) {
+    // Layer 1, super-chunk sc, into A1 buffer `buf`, from this wave's
+    // layer-1 weight fragments in LDS slot `w1s`.
+    auto layer1 = [&](int sc, int buf, const uint8_t *w1s) {
 #pragma unroll
       for (int ii = 0; ii < C::RB1W; ++ii) {
         const int rbl = w * C::RB1W + ii;              // row-block within the chunk
         const int rb = sc * (C::SC / 16) + rbl;
         frag_t wf[C::NQ1];
 #pragma unroll
-        for (int q = 0; q < C::NQ1; ++q) wf[q] = ldg_frag<frag_t>(W1, rb * C::NQ1 + q, lane);
-        const f4 bias = *(const f4 *)(a.b[0] + 16 * rb + 4 * g);
+        for (int q = 0; q < C::NQ1; ++q) wf[q] = lds_frag<frag_t>(w1s, ii * C::NQ1 + q, lane);
+        const f4 bias = *(const f4 *)(B1 + 16 * rb + 4 * g);
         uint8_t *dst = A1 + buf * C::QSC * C::QBYTES;
         const int q2l = rbl / RPQ, j0 = 4 * (rbl % RPQ);
 #pragma unroll
@@ -181,59 +244,101 @@ __global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
     f4 acc2[S2::T];
 #pragma unroll
     for (int i = 0; i < S2::F; ++i) {
-      const f4 bias = Op::SCALED ? f4{0.f, 0.f, 0.f, 0.f}
-                                 : *(const f4 *)(a.b[1] + 16 * (w * S2::F + i) + 4 * g);
+      const f4 bias = Op::SCALED ? f4{0.f, 0.f, 0.f, 0.f} : *(const f4 *)(B2 + 16 * (w * S2::F + i) + 4 * g);
 #pragma unroll
       for (int cb = 0; cb < CB; ++cb) acc2[i * CB + cb] = bias;
     }
 #pragma unroll
     for (int k = 0; k < S2::NREM; ++k)
-      acc2[S2::F * CB + k] = Op::SCALED ? f4{0.f, 0.f, 0.f, 0.f}
-                                        : *(const f4 *)(a.b[1] + 16 * S2::rem_rb(w, k) + 4 * g);
+      acc2[S2::F * CB + k] = Op::SCALED ? f4{0.f, 0.f, 0.f, 0.f} : *(const f4 *)(B2 + 16 * S2::rem_rb(w, k) + 4 * g);
 
-    layer1(0, 0);
-    __syncthreads();
-    constexpr int NW2 = S2::F + S2::NREM;
-    frag_t wc[NW2];
+    // Weight streaming.  Each wave copies its own fragments straight into
+    // LDS: layer-2 k-step q into ring slot q & 1, issued right after k-step
+    // q - 2 was consumed; layer-1 chunk c into slot c & 1, issued after chunk
+    // c - 2 was consumed.  Copies are issued unconditionally (indices clamped
+    // at the end) so the number in flight follows one pattern, and the waits
+    // below count exactly the copies issued after the awaited ones (in-order
+    // completion); any other memory operation only makes a wait stronger.
+    constexpr int NW2 = C::NW2;
+    constexpr int D2 = NW2 * (FRAG / 16);                   // copies per layer-2 k-step
+    constexpr int D1 = C::NW1 * (FRAG / 16);                // copies per layer-1 chunk
+    uint8_t *const ring2 = A2 + w * C::RING_SLOT;
+    uint8_t *const ring1 = smem + C::LDS_W1 + w * (C::NW1 * 64 * FRAG);
+    auto w2slot = [&](int q) { return ring2 + (q & 1) * 4 * C::RING_SLOT; };
+    auto w1slot = [&](int c) { return ring1 + (c & 1) * 4 * (C::NW1 * 64 * FRAG); };
+    // The ring slot follows the position in the copy sequence; only the
+    // source index is clamped (layer 2) or wrapped (layer 1) past the end.
+    auto issue_w2 = [&](int q) {
+      uint8_t *dst = w2slot(q);
+      const int qs = q < C::NQ2 ? q : C::NQ2 - 1;
 #pragma unroll
-    for (int i = 0; i < S2::F; ++i) wc[i] = ldg_frag<frag_t>(W2, (w * S2::F + i) * C::NQ2, lane);
+      for (int i = 0; i < NW2; ++i) {
+        const int rb = i < S2::F ? w * S2::F + i : S2::rem_rb(w, i - S2::F);
+        dma_frag<FRAG>(W2, rb * C::NQ2 + qs, lane, dst + i * 64 * FRAG);
+      }
+    };
+    auto issue_w1 = [&](int c) {
+      uint8_t *dst = w1slot(c);
+      const int cs = c % C::NSC;
 #pragma unroll
-    for (int k = 0; k < S2::NREM; ++k)
-      wc[S2::F + k] = ldg_frag<frag_t>(W2, S2::rem_rb(w, k) * C::NQ2, lane);
+      for (int ii = 0; ii < C::RB1W; ++ii)
+#pragma unroll
+        for (int q = 0; q < C::NQ1; ++q) {
+          const int rb = cs * (C::SC / 16) + w * C::RB1W + ii;
+          dma_frag<FRAG>(W1, rb * C::NQ1 + q, lane, dst + (ii * C::NQ1 + q) * 64 * FRAG);
+        }
+    };
+    issue_w1(0);
+    issue_w1(1);
+    issue_w2(0);
+    issue_w2(1);
+    wait_vmem<0>();
+    layer1(0, 0, w1slot(0));
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    issue_w1(2);
+    lds_barrier();
 
     for (int sc = 0; sc < C::NSC; ++sc) {
-      // next chunk of layer 1 (the last iteration recomputes chunk 0 into the
-      // idle buffer, which keeps the loop body branch-free)
+      // layer 1 of the next chunk (the last iteration recomputes chunk 0 into
+      // the idle buffer, which keeps the loop body branch-free)
       const int nsc = (sc + 1 == C::NSC) ? 0 : sc + 1;
-      layer1(nsc, (sc + 1) & 1);
+      if (sc >= 2) wait_vmem<cap63(2 * C::QSC * D2 + D1)>();   // W1(sc+1), issued in iteration sc-2
+      else wait_vmem<cap63(C::QSC * D2 + D1)>();                // ... or at the end of the prologue
+      layer1(nsc, (sc + 1) & 1, w1slot(sc + 1));
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+      issue_w1(sc + 3);
       const uint8_t *src = A1 + (sc & 1) * C::QSC * C::QBYTES;
 #pragma unroll
       for (int ql = 0; ql < C::QSC; ++ql) {
         const int q = sc * C::QSC + ql;
-        const int qn = (q + 1 < C::NQ2) ? q + 1 : q;
-        frag_t wn[NW2];
-#pragma unroll
-        for (int i = 0; i < S2::F; ++i) wn[i] = ldg_frag<frag_t>(W2, (w * S2::F + i) * C::NQ2 + qn, lane);
-#pragma unroll
-        for (int k = 0; k < S2::NREM; ++k)
-          wn[S2::F + k] = ldg_frag<frag_t>(W2, S2::rem_rb(w, k) * C::NQ2 + qn, lane);
+        // issued after k-step q: the previous k-step's copies and, when q - 2
+        // fell in the previous chunk, this chunk's layer-1 copies
+        if (ql < 2) wait_vmem<D2 + D1>();
+        else wait_vmem<D2>();
+        const uint8_t *wsrc = w2slot(q);
         frag_t af[CB];
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) af[cb] = lds_frag<frag_t>(src, ql * CB + cb, lane);
 #pragma unroll
-        for (int i = 0; i < S2::F; ++i)
+        for (int i = 0; i < S2::F; ++i) {
+          const frag_t wf = lds_frag<frag_t>(wsrc, i, lane);
 #pragma unroll
-          for (int cb = 0; cb < CB; ++cb) acc2[i * CB + cb] = Op::mma(wc[i], af[cb], acc2[i * CB + cb]);
-#pragma unroll
-        for (int k = 0; k < S2::NREM; ++k) {
-          const frag_t ar = lds_frag<frag_t>(src, ql * CB + S2::rem_cb(w, k), lane);
-          acc2[S2::F * CB + k] = Op::mma(wc[S2::F + k], ar, acc2[S2::F * CB + k]);
+          for (int cb = 0; cb < CB; ++cb) acc2[i * CB + cb] = Op::mma(wf, af[cb], acc2[i * CB + cb]);
         }
 #pragma unroll
-        for (int i = 0; i < NW2; ++i) wc[i] = wn[i];
+        for (int k = 0; k < S2::NREM; ++k) {
+          const frag_t wf = lds_frag<frag_t>(wsrc, S2::F + k, lane);
+          const frag_t ar = lds_frag<frag_t>(src, ql * CB + S2::rem_cb(w, k), lane);
+          acc2[S2::F * CB + k] = Op::mma(wf, ar, acc2[S2::F * CB + k]);
+        }
+        // the slot's fragments are in registers before it is refilled
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        issue_w2(q + 2);
       }
-      __syncthreads();
+      lds_barrier();
     }
+    wait_vmem<0>();
+    __syncthreads();
 
     // layer-2 activation -> LDS (layer-3 B fragments)
     auto put = [&](uint8_t *base, int rb, int cb, f4 y) {
@@ -244,7 +349,7 @@ __global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
       for (int t = 0; t < S2::T; ++t) {
         const int rb = t < S2::F * CB ? w * S2::F + t / CB : S2::rem_rb(w, t - S2::F * CB);
         const int cb = t < S2::F * CB ? t % CB : S2::rem_cb(w, t - S2::F * CB);
-        f4 bias = Op::SCALED ? *(const f4 *)(a.b[1] + 16 * rb + 4 * g) : f4{0.f, 0.f, 0.f, 0.f};
+        f4 bias = Op::SCALED ? *(const f4 *)(B2 + 16 * rb + 4 * g) : f4{0.f, 0.f, 0.f, 0.f};
         f4 y;
 #pragma unroll
         for (int r = 0; r < 4; ++r)
@@ -263,14 +368,14 @@ __global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
 #pragma unroll
     for (int i = 0; i < S3::F; ++i) {
       const f4 bias = Op::SCALED ? f4{0.f, 0.f, 0.f, 0.f}
-                                 : *(const f4 *)(a.b[2] + 16 * (w * S3::F + i) + 4 * g);
+                                 : *(const f4 *)(B3 + 16 * (w * S3::F + i) + 4 * g);
 #pragma unroll
       for (int cb = 0; cb < CB; ++cb) acc3[i * CB + cb] = bias;
     }
 #pragma unroll
     for (int k = 0; k < S3::NREM; ++k)
       acc3[S3::F * CB + k] = Op::SCALED ? f4{0.f, 0.f, 0.f, 0.f}
-                                        : *(const f4 *)(a.b[2] + 16 * S3::rem_rb(w, k) + 4 * g);
+                                        : *(const f4 *)(B3 + 16 * S3::rem_rb(w, k) + 4 * g);
     {
       constexpr int NW3 = S3::F + S3::NREM;
       frag_t wc3[NW3];
@@ -309,7 +414,7 @@ __global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
       for (int t = 0; t < S3::T; ++t) {
         const int rb = t < S3::F * CB ? w * S3::F + t / CB : S3::rem_rb(w, t - S3::F * CB);
         const int cb = t < S3::F * CB ? t % CB : S3::rem_cb(w, t - S3::F * CB);
-        f4 bias = Op::SCALED ? *(const f4 *)(a.b[2] + 16 * rb + 4 * g) : f4{0.f, 0.f, 0.f, 0.f};
+        f4 bias = Op::SCALED ? *(const f4 *)(B3 + 16 * rb + 4 * g) : f4{0.f, 0.f, 0.f, 0.f};
         f4 y;
 #pragma unroll
         for (int r = 0; r < 4; ++r)
@@ -329,7 +434,7 @@ __global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
       f4 o[2];
 #pragma unroll
       for (int rb = 0; rb < 2; ++rb)
-        o[rb] = Op::SCALED ? f4{0.f, 0.f, 0.f, 0.f} : *(const f4 *)(a.b[3] + 16 * rb + 4 * g);
+        o[rb] = Op::SCALED ? f4{0.f, 0.f, 0.f, 0.f} : *(const f4 *)(B4 + 16 * rb + 4 * g);
       for (int q = 0; q < C::NQ4; ++q) {
         const frag_t af = lds_frag<frag_t>(A2, q * CB + w, lane);
 #pragma unroll
@@ -338,7 +443,7 @@ __global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
       if (Op::SCALED)
 #pragma unroll
         for (int rb = 0; rb < 2; ++rb) {
-          const f4 bias = *(const f4 *)(a.b[3] + 16 * rb + 4 * g);
+          const f4 bias = *(const f4 *)(B4 + 16 * rb + 4 * g);
 #pragma unroll
           for (int r = 0; r < 4; ++r) o[rb][r] = __builtin_fmaf(o[rb][r], sout[3], bias[r]);
         }
