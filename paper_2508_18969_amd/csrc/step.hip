@@ -57,7 +57,9 @@ template <class Op_, int CB_, int H1_, int H2_, int H3_> struct Cfg {
   static constexpr int NW1 = RB1W * NQ1;             // layer-1 fragments per wave per chunk
   static constexpr int NBIAS = H1P + H2P + H3P + 32; // biases of all layers, FP32
   static constexpr int LDS_BIAS = 0;
-  static constexpr int LDS_A0 = roundup(NBIAS * 4, 256);
+  static constexpr int LDS_DC = roundup(NBIAS * 4, 16);          // DConst block (FP64)
+  static constexpr int LDS_FC = LDS_DC + DConst::N * 8;          // FConst block (FP32)
+  static constexpr int LDS_A0 = roundup(LDS_FC + FConst::N * 4, 256);
   static constexpr int LDS_A1 = LDS_A0 + NQ1 * QBYTES;
   static constexpr int LDS_W1 = LDS_A1 + 2 * QSC * QBYTES;  // two-slot per-wave layer-1 ring
   static constexpr int LDS_A2 = LDS_W1 + 2 * 4 * NW1 * 64 * FRAG;
@@ -73,12 +75,14 @@ template <class Op_, int CB_, int H1_, int H2_, int H3_> struct Cfg {
 
 // One wave copies fragment block `idx` (64 lanes x FRAG bytes) from global
 // memory straight into LDS at `dst` (wave-uniform), bypassing registers.
+typedef const __attribute__((address_space(1))) uint8_t *gptr;
+
 // Addresses are formed as a wave-uniform block base plus a 32-bit lane
 // offset, so the loads use a scalar base register and one shared offset VGPR.
 template <int FRAG>
-__device__ __forceinline__ void dma_frag(const uint8_t *base, int idx, int lane, uint8_t *dst) {
+__device__ __forceinline__ void dma_frag(gptr base, int idx, int lane, uint8_t *dst) {
   static_assert(FRAG == 16 || FRAG == 32, "fragment size");
-  const uint8_t *blk = base + (size_t)idx * (64 * FRAG);
+  gptr blk = base + (size_t)idx * (64 * FRAG);
 #pragma unroll
   for (int h = 0; h < FRAG / 16; ++h)
     __builtin_amdgcn_global_load_lds(
@@ -91,6 +95,31 @@ __device__ __forceinline__ void dma_frag(const uint8_t *base, int idx, int lane,
 // vmcnt is a 6-bit counter: a larger bound is replaced by 63, which waits
 // for more copies than needed and is therefore still safe.
 constexpr int cap63(int n) { return n > 63 ? 63 : n; }
+// Steady-state copy order of the layer-1/2 weight stream, chunk c (QSC
+// layer-2 k-steps per chunk): after consuming k-step (c, ql) a wave issues the
+// layer-2 copies of k-step QSC c + ql + 2 (d2 instructions) and, after ql = 0,
+// the layer-1 copies of chunk c + 3 (d1 instructions).  Before k-step (c, ql)
+// it needs layer-2 k-step QSC c + ql and, at ql = 0, layer-1 chunk c + 1.
+// Returns how many copy instructions were issued after the latest needed one,
+// i.e. the vmcnt that guarantees all needed copies have landed.
+constexpr int copies_after(int qsc, int d1, int d2, int ql) {
+  // walk chunks c-3 .. c (c = 3) in issue order
+  int pos = 0, need_end = -1, total_before_now = 0;
+  const int c = 3, qneed = qsc * c + ql;
+  for (int cc = 0; cc <= c; ++cc)
+    for (int l = 0; l < qsc; ++l) {
+      if (cc == c && l == ql) { total_before_now = pos; cc = c + 1; break; }
+      const int q2 = qsc * cc + l + 2;                // layer-2 k-step copied now
+      pos += d2;
+      if (q2 == qneed) need_end = pos;
+      if (l == 0) {
+        pos += d1;
+        if (ql == 0 && cc + 3 == c + 1) need_end = need_end > pos ? need_end : pos;
+      }
+    }
+  return need_end < 0 ? 0 : total_before_now - need_end;
+}
+
 template <int N>
 __device__ __forceinline__ void wait_vmem() {
   static_assert(N >= 0 && N < 64, "vmcnt range");
@@ -104,9 +133,9 @@ __device__ __forceinline__ void lds_barrier() {
 }
 
 template <class frag_t>
-__device__ __forceinline__ frag_t ldg_frag(const uint8_t *base, int idx, int lane) {
-  const uint8_t *blk = base + (size_t)idx * (64 * sizeof(frag_t));
-  return *(const frag_t *)(blk + (uint32_t)(lane * sizeof(frag_t)));
+__device__ __forceinline__ frag_t ldg_frag(gptr base, int idx, int lane) {
+  gptr blk = base + (size_t)idx * (64 * sizeof(frag_t));
+  return *(const __attribute__((address_space(1))) frag_t *)(blk + (uint32_t)(lane * sizeof(frag_t)));
 }
 template <class frag_t>
 __device__ __forceinline__ frag_t lds_frag(const uint8_t *base, int idx, int lane) {
@@ -153,35 +182,50 @@ __global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
   }
   const float *const B1 = Bl, *const B2 = Bl + C::H1P, *const B3 = Bl + C::H1P + C::H2P;
   const float *const B4 = Bl + C::H1P + C::H2P + C::H3P;
+  // transform and thermodynamic constants too
+  double *const dcl = (double *)(smem + C::LDS_DC);
+  float *const fcl = (float *)(smem + C::LDS_FC);
+  for (int i = threadIdx.x; i < DConst::N; i += blockDim.x) dcl[i] = a.dc[i];
+  for (int i = threadIdx.x; i < FConst::N; i += blockDim.x) fcl[i] = a.fc[i];
   __syncthreads();
 
   for (int64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
     const int64_t cell0 = tile * C::MC;
     // Opaque copies of the weight bases: address arithmetic is redone per tile
     // instead of being hoisted out of the tile loop and kept live (spilled).
-    const uint8_t *W1 = W1g, *W2 = W2g, *W3 = W3g, *W4 = W4g;
-    asm volatile("" : "+s"(W1), "+s"(W2), "+s"(W3), "+s"(W4));
+    const uint8_t *W1o = W1g, *W2o = W2g, *W3o = W3g, *W4o = W4g;
+    asm volatile("" : "+s"(W1o), "+s"(W2o), "+s"(W3o), "+s"(W4o));
+    gptr W1 = (gptr)W1o, W2 = (gptr)W2o, W3 = (gptr)W3o, W4 = (gptr)W4o;
 
     // ------------------------------------------------------------ preprocess
     // Lane (cell 16w + cl, group g) computes input features f = 16h + 4g + r.
     if (w < CB) {
       const int64_t i = cell0 + 16 * w + cl;
       const bool valid = i < a.n;
+      const int64_t ii = valid ? i : 0;
+      // all loads first (one latency), then the arithmetic
+      double xin[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int f = 16 * (j >> 2) + 4 * g + (j & 3);
+        const int s = f - 2 < a.S ? f - 2 : a.S - 1;
+        xin[j] = f == 0 ? a.T[ii] : f == 1 ? a.P[ii] : a.Y[(int64_t)(s > 0 ? s : 0) * a.ld + ii];
+      }
       f4 v[2];
 #pragma unroll
       for (int h = 0; h < 2; ++h)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int f = 16 * h + 4 * g + r;
+          const double x = xin[4 * h + r];
           float z = 0.0f;
           if (valid) {
             if (f == 0)
-              z = (float)((a.T[i] - dc[DConst::T_MU]) * dc[DConst::T_IS]);
+              z = (float)((x - dcl[DConst::T_MU]) * dcl[DConst::T_IS]);
             else if (f == 1)
-              z = (float)((a.P[i] - dc[DConst::P_MU]) * dc[DConst::P_IS]);
+              z = (float)((x - dcl[DConst::P_MU]) * dcl[DConst::P_IS]);
             else if (f - 2 < a.S)
-              z = __builtin_fmaf(ypow(a.Y[(int64_t)(f - 2) * a.ld + i], lam), fc[FConst::ZA + f],
-                                 fc[FConst::ZC + f]);
+              z = __builtin_fmaf(ypow(x, lam), fcl[FConst::ZA + f], fcl[FConst::ZC + f]);
           }
           if (CALIB) amx[0] = umaxf(amx[0], __builtin_fabsf(z));
           v[h][r] = z * inv_sa[0];
@@ -201,11 +245,6 @@ __global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
     }
     __syncthreads();
 
-    frag_t a0[C::NQ1][CB];
-#pragma unroll
-    for (int q = 0; q < C::NQ1; ++q)
-#pragma unroll
-      for (int cb = 0; cb < CB; ++cb) a0[q][cb] = lds_frag<frag_t>(A0, q * CB + cb, lane);
 
     // Layer 1, super-chunk sc, into A1 buffer `buf`, from this wave's
     // layer-1 weight fragments in LDS slot `w1s`.
@@ -218,6 +257,11 @@ __global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
 #pragma unroll
         for (int q = 0; q < C::NQ1; ++q) wf[q] = lds_frag<frag_t>(w1s, ii * C::NQ1 + q, lane);
         const f4 bias = *(const f4 *)(B1 + 16 * rb + 4 * g);
+        frag_t a0[C::NQ1][CB];            // re-read per chunk: cheaper than 16 live registers
+#pragma unroll
+        for (int q = 0; q < C::NQ1; ++q)
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb) a0[q][cb] = lds_frag<frag_t>(A0, q * CB + cb, lane);
         uint8_t *dst = A1 + buf * C::QSC * C::QBYTES;
         const int q2l = rbl / RPQ, j0 = 4 * (rbl % RPQ);
 #pragma unroll
@@ -298,42 +342,52 @@ __global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
     issue_w1(2);
     lds_barrier();
 
+#pragma nounroll
     for (int sc = 0; sc < C::NSC; ++sc) {
       // layer 1 of the next chunk (the last iteration recomputes chunk 0 into
-      // the idle buffer, which keeps the loop body branch-free)
+      // the idle buffer, which keeps the loop body branch-free) follows the
+      // first k-step's matrix products in program order, so its activation
+      // arithmetic can issue while those products execute
       const int nsc = (sc + 1 == C::NSC) ? 0 : sc + 1;
-      if (sc >= 2) wait_vmem<cap63(2 * C::QSC * D2 + D1)>();   // W1(sc+1), issued in iteration sc-2
-      else wait_vmem<cap63(C::QSC * D2 + D1)>();                // ... or at the end of the prologue
-      layer1(nsc, (sc + 1) & 1, w1slot(sc + 1));
-      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-      issue_w1(sc + 3);
       const uint8_t *src = A1 + (sc & 1) * C::QSC * C::QBYTES;
 #pragma unroll
       for (int ql = 0; ql < C::QSC; ++ql) {
         const int q = sc * C::QSC + ql;
-        // issued after k-step q: the previous k-step's copies and, when q - 2
-        // fell in the previous chunk, this chunk's layer-1 copies
-        if (ql < 2) wait_vmem<D2 + D1>();
-        else wait_vmem<D2>();
+        static_assert(C::QSC <= 4, "wait table covers four k-steps per chunk");
+        if (sc >= 3) {           // chunks 0-2 follow the prologue's different history
+          constexpr int n0 = cap63(copies_after(C::QSC, D1, D2, 0));
+          constexpr int n1 = cap63(copies_after(C::QSC, D1, D2, 1 < C::QSC ? 1 : 0));
+          constexpr int n2 = cap63(copies_after(C::QSC, D1, D2, 2 < C::QSC ? 2 : 0));
+          constexpr int n3 = cap63(copies_after(C::QSC, D1, D2, 3 < C::QSC ? 3 : 0));
+          if (ql == 0) wait_vmem<n0>();
+          else if (ql == 1) wait_vmem<n1>();
+          else if (ql == 2) wait_vmem<n2>();
+          else wait_vmem<n3>();
+        } else {
+          wait_vmem<0>();
+        }
         const uint8_t *wsrc = w2slot(q);
-        frag_t af[CB];
+        // all of the k-step's operands are read before the first product, so
+        // the LDS latency is paid once per k-step, not once per fragment
+        frag_t af[CB], ar[S2::NREM > 0 ? S2::NREM : 1], wf[NW2];
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) af[cb] = lds_frag<frag_t>(src, ql * CB + cb, lane);
 #pragma unroll
-        for (int i = 0; i < S2::F; ++i) {
-          const frag_t wf = lds_frag<frag_t>(wsrc, i, lane);
+        for (int i = 0; i < NW2; ++i) wf[i] = lds_frag<frag_t>(wsrc, i, lane);
 #pragma unroll
-          for (int cb = 0; cb < CB; ++cb) acc2[i * CB + cb] = Op::mma(wf, af[cb], acc2[i * CB + cb]);
-        }
+        for (int k = 0; k < S2::NREM; ++k) ar[k] = lds_frag<frag_t>(src, ql * CB + S2::rem_cb(w, k), lane);
 #pragma unroll
-        for (int k = 0; k < S2::NREM; ++k) {
-          const frag_t wf = lds_frag<frag_t>(wsrc, S2::F + k, lane);
-          const frag_t ar = lds_frag<frag_t>(src, ql * CB + S2::rem_cb(w, k), lane);
-          acc2[S2::F * CB + k] = Op::mma(wf, ar, acc2[S2::F * CB + k]);
-        }
-        // the slot's fragments are in registers before it is refilled
+        for (int i = 0; i < S2::F; ++i)
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb) acc2[i * CB + cb] = Op::mma(wf[i], af[cb], acc2[i * CB + cb]);
+#pragma unroll
+        for (int k = 0; k < S2::NREM; ++k)
+          acc2[S2::F * CB + k] = Op::mma(wf[S2::F + k], ar[k], acc2[S2::F * CB + k]);
+        if (ql == 0) layer1(nsc, (sc + 1) & 1, w1slot(sc + 1));
+        // the slots' fragments are in registers before they are refilled
         asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
         issue_w2(q + 2);
+        if (ql == 0) issue_w1(sc + 3);
       }
       lds_barrier();
     }
@@ -377,35 +431,58 @@ __global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
       acc3[S3::F * CB + k] = Op::SCALED ? f4{0.f, 0.f, 0.f, 0.f}
                                         : *(const f4 *)(B3 + 16 * S3::rem_rb(w, k) + 4 * g);
     {
+      // fully unrolled: every load index is a constant, so the compiler's
+      // wait counts are exact; weights are fetched three k-steps ahead into a
+      // four-deep register ring and activations one k-step ahead
       constexpr int NW3 = S3::F + S3::NREM;
-      frag_t wc3[NW3];
+      constexpr int PD = 3;                            // weight prefetch distance
+      frag_t w3r[PD + 1][NW3];
+      auto load_w3 = [&](frag_t (&dst)[NW3], int q) {
 #pragma unroll
-      for (int i = 0; i < S3::F; ++i) wc3[i] = ldg_frag<frag_t>(W3, (w * S3::F + i) * C::NQ3, lane);
-#pragma unroll
-      for (int k = 0; k < S3::NREM; ++k)
-        wc3[S3::F + k] = ldg_frag<frag_t>(W3, S3::rem_rb(w, k) * C::NQ3, lane);
-      for (int q = 0; q < C::NQ3; ++q) {
-        const int qn = (q + 1 < C::NQ3) ? q + 1 : q;
-        frag_t wn[NW3];
-#pragma unroll
-        for (int i = 0; i < S3::F; ++i) wn[i] = ldg_frag<frag_t>(W3, (w * S3::F + i) * C::NQ3 + qn, lane);
+        for (int i = 0; i < S3::F; ++i) dst[i] = ldg_frag<frag_t>(W3, (w * S3::F + i) * C::NQ3 + q, lane);
 #pragma unroll
         for (int k = 0; k < S3::NREM; ++k)
-          wn[S3::F + k] = ldg_frag<frag_t>(W3, S3::rem_rb(w, k) * C::NQ3 + qn, lane);
-        frag_t af[CB];
+          dst[S3::F + k] = ldg_frag<frag_t>(W3, S3::rem_rb(w, k) * C::NQ3 + q, lane);
+      };
+      frag_t a3r[2][CB + (S3::NREM > 0 ? S3::NREM : 1)];
+      auto load_a3 = [&](frag_t (&dst)[CB + (S3::NREM > 0 ? S3::NREM : 1)], int q) {
 #pragma unroll
-        for (int cb = 0; cb < CB; ++cb) af[cb] = lds_frag<frag_t>(A2, q * CB + cb, lane);
+        for (int cb = 0; cb < CB; ++cb) dst[cb] = lds_frag<frag_t>(A2, q * CB + cb, lane);
+#pragma unroll
+        for (int k = 0; k < S3::NREM; ++k) dst[CB + k] = lds_frag<frag_t>(A2, q * CB + S3::rem_cb(w, k), lane);
+      };
+#pragma unroll
+      for (int q = 0; q < PD; ++q)
+        if (q < C::NQ3) load_w3(w3r[q], q);
+      load_a3(a3r[0], 0);
+#pragma unroll
+      for (int q = 0; q < C::NQ3; ++q) {
+        if (q + PD < C::NQ3) load_w3(w3r[(q + PD) % (PD + 1)], q + PD);
+        if (q + 1 < C::NQ3) load_a3(a3r[(q + 1) & 1], q + 1);
+        const frag_t(&wc3)[NW3] = w3r[q % (PD + 1)];
+        const auto &ac = a3r[q & 1];
 #pragma unroll
         for (int i = 0; i < S3::F; ++i)
 #pragma unroll
-          for (int cb = 0; cb < CB; ++cb) acc3[i * CB + cb] = Op::mma(wc3[i], af[cb], acc3[i * CB + cb]);
+          for (int cb = 0; cb < CB; ++cb) acc3[i * CB + cb] = Op::mma(wc3[i], ac[cb], acc3[i * CB + cb]);
 #pragma unroll
-        for (int k = 0; k < S3::NREM; ++k) {
-          const frag_t ar = lds_frag<frag_t>(A2, q * CB + S3::rem_cb(w, k), lane);
-          acc3[S3::F * CB + k] = Op::mma(wc3[S3::F + k], ar, acc3[S3::F * CB + k]);
-        }
+        for (int k = 0; k < S3::NREM; ++k)
+          acc3[S3::F * CB + k] = Op::mma(wc3[S3::F + k], ac[CB + k], acc3[S3::F * CB + k]);
+      }
+    }
+    // The state of the post-processing is fetched now, so its latency
+    // overlaps the layer-3 activation phase.
+    double Tc = 0.0, Pc = 0.0, Yc[8];
+    const int64_t ipost = cell0 + 16 * w + cl;
+    const bool vpost = ipost < a.n;
+    const int64_t icp = vpost ? ipost : 0;
+    if (!CALIB && w < CB) {
+      Tc = a.T[icp];
+      Pc = a.P[icp];
 #pragma unroll
-        for (int i = 0; i < NW3; ++i) wc3[i] = wn[i];
+      for (int j = 0; j < 8; ++j) {
+        const int s = 16 * (j >> 2) + 4 * g + (j & 3) - 2;
+        Yc[j] = (s >= 0 && s < a.S) ? a.Y[(int64_t)s * a.ld + icp] : 0.0;
       }
     }
     __syncthreads();  // every wave is done reading the layer-2 activation
@@ -435,10 +512,17 @@ __global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
 #pragma unroll
       for (int rb = 0; rb < 2; ++rb)
         o[rb] = Op::SCALED ? f4{0.f, 0.f, 0.f, 0.f} : *(const f4 *)(B4 + 16 * rb + 4 * g);
+      // all layer-4 fragments in flight at once
+      frag_t w4r[2][C::NQ4];
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int q = 0; q < C::NQ4; ++q) w4r[rb][q] = ldg_frag<frag_t>(W4, rb * C::NQ4 + q, lane);
+#pragma unroll
       for (int q = 0; q < C::NQ4; ++q) {
         const frag_t af = lds_frag<frag_t>(A2, q * CB + w, lane);
 #pragma unroll
-        for (int rb = 0; rb < 2; ++rb) o[rb] = Op::mma(ldg_frag<frag_t>(W4, rb * C::NQ4 + q, lane), af, o[rb]);
+        for (int rb = 0; rb < 2; ++rb) o[rb] = Op::mma(w4r[rb][q], af, o[rb]);
       }
       if (Op::SCALED)
 #pragma unroll
@@ -449,14 +533,13 @@ __global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
         }
 
       // post: lane holds output rows rho = 16h + 4g + r, species s = rho - 2
-      const int64_t i = cell0 + 16 * w + cl;
-      const bool valid = i < a.n;
-      const int64_t ic = valid ? i : 0;
-      const double T = a.T[ic], P = a.P[ic];
+      const int64_t i = ipost;
+      const bool valid = vpost;
+      const double T = Tc, P = Pc;
       bool bad = !__builtin_isfinite(T) || !__builtin_isfinite(P);
       double Y[8], Yh[8];
       double ssum = 0.0, h0 = 0.0;
-      const double t_ref = dc[DConst::T_REF];
+      const double t_ref = dcl[DConst::T_REF];
 #pragma unroll
       for (int h = 0; h < 2; ++h)
 #pragma unroll
@@ -465,11 +548,11 @@ __global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
           Y[j] = 0.0;
           Yh[j] = 0.0;
           if (s >= 0 && s < a.S) {
-            const double y = a.Y[(int64_t)s * a.ld + ic];
+            const double y = Yc[j];
             Y[j] = y;
             bad |= !__builtin_isfinite(y);
             const float b = ypow(y, lam);
-            const float wv = __builtin_fmaf(o[h][r], fc[FConst::PA + rho], fc[FConst::PB + rho]);
+            const float wv = __builtin_fmaf(o[h][r], fcl[FConst::PA + rho], fcl[FConst::PB + rho]);
             double dy;
             if (b > 0.0f && __builtin_fabsf(wv) <= 0.5f * b) {
               // Y* - Y = Y ((1 + wv/b)^(1/lam) - 1), no cancellation for small steps
@@ -486,7 +569,7 @@ __global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
             yh = yh > 0.0 ? yh : 0.0;
             Yh[j] = yh;
             ssum += yh;
-            if (a.thermo) h0 += y * (dc[DConst::HF + rho] + dc[DConst::CP + rho] * (T - t_ref));
+            if (a.thermo) h0 += y * (dcl[DConst::HF + rho] + dcl[DConst::CP + rho] * (T - t_ref));
           }
         }
       // the cell's four lanes: l, l^16, l^32, l^48
@@ -502,8 +585,8 @@ __global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
         Yn[j] = Yh[j] / ssum;
         const int rho = 16 * (j >> 2) + 4 * g + (j & 3);
         if (a.thermo && rho >= 2 && rho - 2 < a.S) {
-          hn += Yn[j] * dc[DConst::HF + rho];
-          cn += Yn[j] * dc[DConst::CP + rho];
+          hn += Yn[j] * dcl[DConst::HF + rho];
+          cn += Yn[j] * dcl[DConst::CP + rho];
         }
       }
       double Tn = T;
