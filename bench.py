@@ -8,6 +8,11 @@ FP32, FP16 and FP8 are timed the same way and listed under `precisions`,
 each with its max-abs dY and T error against the FP64 oracle on a sample.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Counter runs: `--copy-probe BYTES` adds one plain device-to-device copy of that
+many bytes before the timed region, whose FETCH_SIZE / WRITE_SIZE readings
+calibrate the counters; `--traffic FETCH.csv WRITE.csv` turns two rocprofv3
+--pmc counter files of such a run into the stored per-launch traffic record.
 """
 from __future__ import annotations
 
@@ -58,7 +63,14 @@ def main():
     ap.add_argument("--cells", type=int, default=1 << 20)
     ap.add_argument("--precisions", default="fp32,bf16,fp16,fp8")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline leg")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="bytes of one plain device copy run before the timed region")
+    ap.add_argument("--traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the per-launch HBM traffic record from two counter runs")
     args = ap.parse_args()
+    if args.traffic:
+        write_traffic(args.traffic[0], args.traffic[1], args.cells, args.copy_probe)
+        return
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; the chemistry update needs no "
               "communication (cells are independent) - run with --gpus 1", file=sys.stderr)
@@ -123,6 +135,13 @@ def main():
                          "mfma_frac": tflops / PEAK_TFLOPS[prec], "steps": k}
         h.close()
 
+    if args.copy_probe:
+        src = torch.empty(args.copy_probe // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     # timed headline run: BF16, exactly K steps between synchronisations
     h = handle("bf16")
     for _ in range(args.warmup):
@@ -173,6 +192,43 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def _counter_means(path, name_part):
+    """Mean of each counter over the dispatches whose kernel name contains
+    name_part (rocprofv3 counter_collection CSV, values in KiB)."""
+    import csv
+    acc = {}
+    for r in csv.DictReader(open(path)):
+        if name_part in r["Kernel_Name"]:
+            acc.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in acc.items()}
+
+
+def write_traffic(fetch_csv, write_csv, n_cells, copy_bytes):
+    """HBM bytes per launch of the chemistry kernel: FETCH_SIZE + WRITE_SIZE,
+    each scaled by bytes/reading of the plain copy of copy_bytes bytes (which
+    reads and writes copy_bytes each)."""
+    if copy_bytes <= 0:
+        sys.exit("--traffic needs --copy-probe BYTES of the counter runs")
+    f_k = _counter_means(fetch_csv, "chem_step")["FETCH_SIZE"]
+    w_k = _counter_means(write_csv, "chem_step")["WRITE_SIZE"]
+    # the copy is the largest other dispatch of the run
+    import csv
+    f_c = max(float(r["Counter_Value"]) for r in csv.DictReader(open(fetch_csv))
+              if "chem_step" not in r["Kernel_Name"] and r["Counter_Name"] == "FETCH_SIZE")
+    w_c = max(float(r["Counter_Value"]) for r in csv.DictReader(open(write_csv))
+              if "chem_step" not in r["Kernel_Name"] and r["Counter_Name"] == "WRITE_SIZE")
+    fs, ws = copy_bytes / f_c, copy_bytes / w_c
+    rec = {"kernel_sha": kernel_sha(), "cells": n_cells,
+           "fetch_kib_per_launch": f_k, "write_kib_per_launch": w_k,
+           "copy_bytes": copy_bytes, "copy_fetch_kib": f_c, "copy_write_kib": w_c,
+           "fetch_bytes_per_reading": fs, "write_bytes_per_reading": ws,
+           "hbm_bytes_per_launch": f_k * fs + w_k * ws,
+           "algorithmic_state_bytes": STATE_BYTES_PER_CELL * n_cells}
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec))
 
 
 def cpu_baseline(st, net, thermo, sample, outputs, results):

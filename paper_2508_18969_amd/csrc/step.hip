@@ -553,18 +553,22 @@ __global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
             bad |= !__builtin_isfinite(y);
             const float b = ypow(y, lam);
             const float wv = __builtin_fmaf(o[h][r], fcl[FConst::PA + rho], fcl[FConst::PB + rho]);
-            double dy;
-            if (b > 0.0f && __builtin_fabsf(wv) <= 0.5f * b) {
-              // Y* - Y = Y ((1 + wv/b)^(1/lam) - 1), no cancellation for small steps
-              const float em1 = expm1f(log1pf(wv / b) * inv_lam);
-              dy = y * (double)em1;
-            } else {
-              // Y* = (Y^lam + lam delta)^(1/lam), clamped at 0
-              const float base = b + wv;
-              const double ystar =
-                  base > 0.0f ? (double)__builtin_amdgcn_exp2f(__builtin_amdgcn_logf(base) * inv_lam) : 0.0;
-              dy = ystar - y;
-            }
+            // Inverse Box-Cox, Y* = (b + wv)^(1/lam) clamped at 0.  For a small
+            // step it is taken relative to Y, Y* - Y = Y ((1 + t)^(1/lam) - 1)
+            // with t = wv / b, which has no cancellation.  Both forms are
+            // evaluated without branches on the hardware log2 / exp2.
+            const float t = wv * __builtin_amdgcn_rcpf(b);
+            const bool small = b > 0.0f && __builtin_fabsf(t) <= 0.5f;
+            const float u = 1.0f + t;
+            // log2(1 + t) = log2(u) t / (u - 1) for the rounded u (exact when u == 1)
+            const float l1p = u == 1.0f ? t * kLog2e
+                                        : __builtin_amdgcn_logf(u) * (t * __builtin_amdgcn_rcpf(u - 1.0f));
+            const float base = b + wv;
+            const float z = (small ? l1p : __builtin_amdgcn_logf(base)) * inv_lam;
+            const float e = __builtin_amdgcn_exp2f(z);
+            // 2^z - 1 = (e - 1) z / log2(e) for the rounded e = 2^z
+            const float em1 = e == 1.0f ? z * kLn2 : (e - 1.0f) * (z * __builtin_amdgcn_rcpf(__builtin_amdgcn_logf(e)));
+            const double dy = small ? y * (double)em1 : (base > 0.0f ? (double)e : 0.0) - y;
             double yh = y + dy;
             yh = yh > 0.0 ? yh : 0.0;
             Yh[j] = yh;
@@ -580,9 +584,10 @@ __global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
       badi |= __shfl_xor(badi, 32);
       double Yn[8];
       double hn = 0.0, cn = 0.0;
+      const double rsum = 1.0 / ssum;
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
-        Yn[j] = Yh[j] / ssum;
+        Yn[j] = Yh[j] * rsum;
         const int rho = 16 * (j >> 2) + 4 * g + (j & 3);
         if (a.thermo && rho >= 2 && rho - 2 < a.S) {
           hn += Yn[j] * dcl[DConst::HF + rho];
