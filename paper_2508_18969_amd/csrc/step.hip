@@ -12,9 +12,10 @@
 //   L4      layer-3 output reuses that LDS region; linear output layer
 //   post    inverse transform in FP32, update, renormalisation and optional
 //           temperature in FP64, written by the lane that holds the values
-// Waves split every layer's output rows; weights stream from L2 straight
-// into registers with one-k-step-ahead prefetch (each wave reads rows no
-// other wave reads, so weights cross the L2->CU path once per tile).
+// Waves split every layer's output rows, so each wave reads weight rows no
+// other wave reads: weights stream from L2 straight into registers, fetched
+// about two k-steps ahead of their use, and cross the L2->CU path once per
+// tile.  LDS holds only activations, biases and constants.
 #include "common.h"
 #include "internal.h"
 
@@ -61,73 +62,19 @@ template <class Op_, int CB_, int H1_, int H2_, int H3_> struct Cfg {
   static constexpr int LDS_FC = LDS_DC + DConst::N * 8;          // FConst block (FP32)
   static constexpr int LDS_A0 = roundup(LDS_FC + FConst::N * 4, 256);
   static constexpr int LDS_A1 = LDS_A0 + NQ1 * QBYTES;
-  static constexpr int LDS_W1 = LDS_A1 + 2 * QSC * QBYTES;  // two-slot per-wave layer-1 ring
-  static constexpr int LDS_A2 = LDS_W1 + 2 * 4 * NW1 * 64 * FRAG;
-  // layer-2 weights stream through a two-slot per-wave LDS ring that lives in
-  // the region which later holds the layer-2 activation
-  static constexpr int NW2 = S2::F + S2::NREM;               // fragments per wave per k-step
-  static constexpr int RING_SLOT = NW2 * 64 * FRAG;            // one wave, one k-step
-  static constexpr int RING_BYTES = 2 * 4 * RING_SLOT;
+  static constexpr int LDS_A2 = LDS_A1 + 2 * QSC * QBYTES;
+  static constexpr int NW2 = S2::F + S2::NREM;               // layer-2 fragments per wave per k-step
+  static constexpr int NB2 = QSC % 2 == 0 ? 2 : 1;           // layer-2 register buffers
   static constexpr int A2_BYTES = Max<NQ3, NQ4>::v * QBYTES;
-  static constexpr int LDS_BYTES = LDS_A2 + Max<A2_BYTES, RING_BYTES>::v;
+  static constexpr int LDS_BYTES = LDS_A2 + A2_BYTES;
   static_assert(LDS_BYTES <= 160 * 1024, "LDS budget");
 };
 
-// One wave copies fragment block `idx` (64 lanes x FRAG bytes) from global
-// memory straight into LDS at `dst` (wave-uniform), bypassing registers.
+// Pointer into global memory: loads through it are global (not flat) loads.
 typedef const __attribute__((address_space(1))) uint8_t *gptr;
 
-// Addresses are formed as a wave-uniform block base plus a 32-bit lane
-// offset, so the loads use a scalar base register and one shared offset VGPR.
-template <int FRAG>
-__device__ __forceinline__ void dma_frag(gptr base, int idx, int lane, uint8_t *dst) {
-  static_assert(FRAG == 16 || FRAG == 32, "fragment size");
-  gptr blk = base + (size_t)idx * (64 * FRAG);
-#pragma unroll
-  for (int h = 0; h < FRAG / 16; ++h)
-    __builtin_amdgcn_global_load_lds(
-        (const __attribute__((address_space(1))) void *)(blk + (uint32_t)(lane * FRAG + h * 16)),
-        (__attribute__((address_space(3))) void *)(dst + h * 64 * 16), 16, 0, 0);
-}
-// Waits until at most N vector-memory operations of this wave are in flight.
-// Direct-to-LDS copies are not tracked by the compiler's own wait insertion;
-// the memory clobber keeps LDS reads from moving above the wait.
-// vmcnt is a 6-bit counter: a larger bound is replaced by 63, which waits
-// for more copies than needed and is therefore still safe.
-constexpr int cap63(int n) { return n > 63 ? 63 : n; }
-// Steady-state copy order of the layer-1/2 weight stream, chunk c (QSC
-// layer-2 k-steps per chunk): after consuming k-step (c, ql) a wave issues the
-// layer-2 copies of k-step QSC c + ql + 2 (d2 instructions) and, after ql = 0,
-// the layer-1 copies of chunk c + 3 (d1 instructions).  Before k-step (c, ql)
-// it needs layer-2 k-step QSC c + ql and, at ql = 0, layer-1 chunk c + 1.
-// Returns how many copy instructions were issued after the latest needed one,
-// i.e. the vmcnt that guarantees all needed copies have landed.
-constexpr int copies_after(int qsc, int d1, int d2, int ql) {
-  // walk chunks c-3 .. c (c = 3) in issue order
-  int pos = 0, need_end = -1, total_before_now = 0;
-  const int c = 3, qneed = qsc * c + ql;
-  for (int cc = 0; cc <= c; ++cc)
-    for (int l = 0; l < qsc; ++l) {
-      if (cc == c && l == ql) { total_before_now = pos; cc = c + 1; break; }
-      const int q2 = qsc * cc + l + 2;                // layer-2 k-step copied now
-      pos += d2;
-      if (q2 == qneed) need_end = pos;
-      if (l == 0) {
-        pos += d1;
-        if (ql == 0 && cc + 3 == c + 1) need_end = need_end > pos ? need_end : pos;
-      }
-    }
-  return need_end < 0 ? 0 : total_before_now - need_end;
-}
-
-template <int N>
-__device__ __forceinline__ void wait_vmem() {
-  static_assert(N >= 0 && N < 64, "vmcnt range");
-  asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
-}
-
 // Workgroup barrier for LDS traffic only: unlike __syncthreads it does not
-// wait for outstanding global loads, so weight copies stay in flight.
+// wait for outstanding global loads, so weight loads stay in flight.
 __device__ __forceinline__ void lds_barrier() {
   asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
@@ -209,7 +156,7 @@ __global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
       for (int j = 0; j < 8; ++j) {
         const int f = 16 * (j >> 2) + 4 * g + (j & 3);
         const int s = f - 2 < a.S ? f - 2 : a.S - 1;
-        xin[j] = f == 0 ? a.T[ii] : f == 1 ? a.P[ii] : a.Y[(int64_t)(s > 0 ? s : 0) * a.ld + ii];
+        xin[j] = __builtin_nontemporal_load(f == 0 ? &a.T[ii] : f == 1 ? &a.P[ii] : &a.Y[(int64_t)(s > 0 ? s : 0) * a.ld + ii]);
       }
       f4 v[2];
 #pragma unroll
@@ -247,15 +194,13 @@ __global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
 
 
     // Layer 1, super-chunk sc, into A1 buffer `buf`, from this wave's
-    // layer-1 weight fragments in LDS slot `w1s`.
-    auto layer1 = [&](int sc, int buf, const uint8_t *w1s) {
+    // layer-1 weight fragments of that chunk.
+    auto layer1 = [&](int sc, int buf, const frag_t (&w1f)[C::NW1]) {
 #pragma unroll
       for (int ii = 0; ii < C::RB1W; ++ii) {
         const int rbl = w * C::RB1W + ii;              // row-block within the chunk
         const int rb = sc * (C::SC / 16) + rbl;
-        frag_t wf[C::NQ1];
-#pragma unroll
-        for (int q = 0; q < C::NQ1; ++q) wf[q] = lds_frag<frag_t>(w1s, ii * C::NQ1 + q, lane);
+        const frag_t *wf = w1f + ii * C::NQ1;
         const f4 bias = *(const f4 *)(B1 + 16 * rb + 4 * g);
         frag_t a0[C::NQ1][CB];            // re-read per chunk: cheaper than 16 live registers
 #pragma unroll
@@ -296,102 +241,85 @@ __global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
     for (int k = 0; k < S2::NREM; ++k)
       acc2[S2::F * CB + k] = Op::SCALED ? f4{0.f, 0.f, 0.f, 0.f} : *(const f4 *)(B2 + 16 * S2::rem_rb(w, k) + 4 * g);
 
-    // Weight streaming.  Each wave copies its own fragments straight into
-    // LDS: layer-2 k-step q into ring slot q & 1, issued right after k-step
-    // q - 2 was consumed; layer-1 chunk c into slot c & 1, issued after chunk
-    // c - 2 was consumed.  Copies are issued unconditionally (indices clamped
-    // at the end) so the number in flight follows one pattern, and the waits
-    // below count exactly the copies issued after the awaited ones (in-order
-    // completion); any other memory operation only makes a wait stronger.
+    // Weight streaming.  Every wave reads only its own weight rows, so the
+    // fragments go from L2 straight into registers.  Layer 2 keeps one
+    // register buffer per k-step parity: fragment i of k-step q + NB2 is
+    // loaded as soon as the products of k-step q have read fragment i, which
+    // gives each load about NB2 k-steps of matrix work to land.  Layer-1
+    // fragments of chunk c + 2 are loaded once chunk c + 1 has used them.
+    // Past the end the indices are clamped, so the loop body is uniform.
     constexpr int NW2 = C::NW2;
-    constexpr int D2 = NW2 * (FRAG / 16);                   // copies per layer-2 k-step
-    constexpr int D1 = C::NW1 * (FRAG / 16);                // copies per layer-1 chunk
-    uint8_t *const ring2 = A2 + w * C::RING_SLOT;
-    uint8_t *const ring1 = smem + C::LDS_W1 + w * (C::NW1 * 64 * FRAG);
-    auto w2slot = [&](int q) { return ring2 + (q & 1) * 4 * C::RING_SLOT; };
-    auto w1slot = [&](int c) { return ring1 + (c & 1) * 4 * (C::NW1 * 64 * FRAG); };
-    // The ring slot follows the position in the copy sequence; only the
-    // source index is clamped (layer 2) or wrapped (layer 1) past the end.
-    auto issue_w2 = [&](int q) {
-      uint8_t *dst = w2slot(q);
-      const int qs = q < C::NQ2 ? q : C::NQ2 - 1;
-#pragma unroll
-      for (int i = 0; i < NW2; ++i) {
-        const int rb = i < S2::F ? w * S2::F + i : S2::rem_rb(w, i - S2::F);
-        dma_frag<FRAG>(W2, rb * C::NQ2 + qs, lane, dst + i * 64 * FRAG);
-      }
+    constexpr int NB2 = C::NB2;
+    constexpr int NA2 = CB + (S2::NREM > 0 ? S2::NREM : 1);
+    frag_t wb[NB2][NW2];
+    auto w2_load = [&](frag_t &dst, int i, int q) {
+      const int rb = i < S2::F ? w * S2::F + i : S2::rem_rb(w, i - S2::F);
+      dst = ldg_frag<frag_t>(W2, rb * C::NQ2 + (q < C::NQ2 ? q : C::NQ2 - 1), lane);
     };
-    auto issue_w1 = [&](int c) {
-      uint8_t *dst = w1slot(c);
-      const int cs = c % C::NSC;
+    frag_t w1r[C::NW1];
+    auto w1_load = [&](int c) {
+      const int cs = c < C::NSC ? c : c - C::NSC;
 #pragma unroll
       for (int ii = 0; ii < C::RB1W; ++ii)
 #pragma unroll
         for (int q = 0; q < C::NQ1; ++q) {
           const int rb = cs * (C::SC / 16) + w * C::RB1W + ii;
-          dma_frag<FRAG>(W1, rb * C::NQ1 + q, lane, dst + (ii * C::NQ1 + q) * 64 * FRAG);
+          w1r[ii * C::NQ1 + q] = ldg_frag<frag_t>(W1, rb * C::NQ1 + q, lane);
         }
     };
-    issue_w1(0);
-    issue_w1(1);
-    issue_w2(0);
-    issue_w2(1);
-    wait_vmem<0>();
-    layer1(0, 0, w1slot(0));
-    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-    issue_w1(2);
-    lds_barrier();
+    w1_load(0);
+    layer1(0, 0, w1r);
+    w1_load(1);
+#pragma unroll
+    for (int b = 0; b < NB2; ++b)
+#pragma unroll
+      for (int i = 0; i < NW2; ++i) w2_load(wb[b][i], i, b);
+    __syncthreads();
 
 #pragma nounroll
     for (int sc = 0; sc < C::NSC; ++sc) {
       // layer 1 of the next chunk (the last iteration recomputes chunk 0 into
-      // the idle buffer, which keeps the loop body branch-free) follows the
-      // first k-step's matrix products in program order, so its activation
+      // the idle buffer, which keeps the loop body uniform) follows the first
+      // k-step's matrix products in program order, so its activation
       // arithmetic can issue while those products execute
       const int nsc = (sc + 1 == C::NSC) ? 0 : sc + 1;
       const uint8_t *src = A1 + (sc & 1) * C::QSC * C::QBYTES;
+      // the chunk's activation fragments, read once
+      frag_t act[C::QSC][NA2];
+#pragma unroll
+      for (int ql = 0; ql < C::QSC; ++ql) {
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) act[ql][cb] = lds_frag<frag_t>(src, ql * CB + cb, lane);
+#pragma unroll
+        for (int k = 0; k < S2::NREM; ++k) act[ql][CB + k] = lds_frag<frag_t>(src, ql * CB + S2::rem_cb(w, k), lane);
+      }
 #pragma unroll
       for (int ql = 0; ql < C::QSC; ++ql) {
         const int q = sc * C::QSC + ql;
-        static_assert(C::QSC <= 4, "wait table covers four k-steps per chunk");
-        if (sc >= 3) {           // chunks 0-2 follow the prologue's different history
-          constexpr int n0 = cap63(copies_after(C::QSC, D1, D2, 0));
-          constexpr int n1 = cap63(copies_after(C::QSC, D1, D2, 1 < C::QSC ? 1 : 0));
-          constexpr int n2 = cap63(copies_after(C::QSC, D1, D2, 2 < C::QSC ? 2 : 0));
-          constexpr int n3 = cap63(copies_after(C::QSC, D1, D2, 3 < C::QSC ? 3 : 0));
-          if (ql == 0) wait_vmem<n0>();
-          else if (ql == 1) wait_vmem<n1>();
-          else if (ql == 2) wait_vmem<n2>();
-          else wait_vmem<n3>();
-        } else {
-          wait_vmem<0>();
+        frag_t(&wc)[NW2] = wb[ql % NB2];
+        // the scheduling barriers keep each refill right behind the products
+        // that read the fragment (the scheduler would otherwise sink the
+        // loads towards their next use and shorten their lead)
+#pragma unroll
+        for (int i = 0; i < S2::F; ++i) {
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb) acc2[i * CB + cb] = Op::mma(wc[i], act[ql][cb], acc2[i * CB + cb]);
+          w2_load(wc[i], i, q + NB2);
+          __builtin_amdgcn_sched_barrier(0);
         }
-        const uint8_t *wsrc = w2slot(q);
-        // all of the k-step's operands are read before the first product, so
-        // the LDS latency is paid once per k-step, not once per fragment
-        frag_t af[CB], ar[S2::NREM > 0 ? S2::NREM : 1], wf[NW2];
 #pragma unroll
-        for (int cb = 0; cb < CB; ++cb) af[cb] = lds_frag<frag_t>(src, ql * CB + cb, lane);
-#pragma unroll
-        for (int i = 0; i < NW2; ++i) wf[i] = lds_frag<frag_t>(wsrc, i, lane);
-#pragma unroll
-        for (int k = 0; k < S2::NREM; ++k) ar[k] = lds_frag<frag_t>(src, ql * CB + S2::rem_cb(w, k), lane);
-#pragma unroll
-        for (int i = 0; i < S2::F; ++i)
-#pragma unroll
-          for (int cb = 0; cb < CB; ++cb) acc2[i * CB + cb] = Op::mma(wf[i], af[cb], acc2[i * CB + cb]);
-#pragma unroll
-        for (int k = 0; k < S2::NREM; ++k)
-          acc2[S2::F * CB + k] = Op::mma(wf[S2::F + k], ar[k], acc2[S2::F * CB + k]);
-        if (ql == 0) layer1(nsc, (sc + 1) & 1, w1slot(sc + 1));
-        // the slots' fragments are in registers before they are refilled
-        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-        issue_w2(q + 2);
-        if (ql == 0) issue_w1(sc + 3);
+        for (int k = 0; k < S2::NREM; ++k) {
+          acc2[S2::F * CB + k] = Op::mma(wc[S2::F + k], act[ql][CB + k], acc2[S2::F * CB + k]);
+          w2_load(wc[S2::F + k], S2::F + k, q + NB2);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+        if (ql == 0) {
+          layer1(nsc, (sc + 1) & 1, w1r);
+          w1_load(sc + 2);
+        }
       }
       lds_barrier();
     }
-    wait_vmem<0>();
     __syncthreads();
 
     // layer-2 activation -> LDS (layer-3 B fragments)
@@ -477,12 +405,12 @@ __global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
     const bool vpost = ipost < a.n;
     const int64_t icp = vpost ? ipost : 0;
     if (!CALIB && w < CB) {
-      Tc = a.T[icp];
-      Pc = a.P[icp];
+      Tc = __builtin_nontemporal_load(&a.T[icp]);
+      Pc = __builtin_nontemporal_load(&a.P[icp]);
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         const int s = 16 * (j >> 2) + 4 * g + (j & 3) - 2;
-        Yc[j] = (s >= 0 && s < a.S) ? a.Y[(int64_t)s * a.ld + icp] : 0.0;
+        Yc[j] = (s >= 0 && s < a.S) ? __builtin_nontemporal_load(&a.Y[(int64_t)s * a.ld + icp]) : 0.0;
       }
     }
     __syncthreads();  // every wave is done reading the layer-2 activation
@@ -617,10 +545,10 @@ __global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int s = 16 * h + 4 * g + r - 2, j = 4 * h + r;
-            if (s >= 0 && s < a.S) a.Y_out[(int64_t)s * a.ld + i] = okc ? Yn[j] : Y[j];
+            if (s >= 0 && s < a.S) __builtin_nontemporal_store(okc ? Yn[j] : Y[j], &a.Y_out[(int64_t)s * a.ld + i]);
           }
         if (g == 0) {
-          if (a.T_out) a.T_out[i] = okc ? Tn : T;
+          if (a.T_out) __builtin_nontemporal_store(okc ? Tn : T, &a.T_out[i]);
           if (!okc && a.n_bad) atomicAdd(a.n_bad, 1u);
         }
       }
