@@ -33,10 +33,12 @@ template <int R, int CB> struct Split {
   static __device__ __forceinline__ int rem_cb(int w, int k) { return (w * NREM + k) % CB; }
 };
 
-constexpr int padH(int h, int ks, int cb) {
-  int g = ks > 16 ? ks : 16;
-  int p = roundup(h, g);
-  while ((((p / 16) % 4) * cb) % 4) p += g;
+// Output rows a layer computes: h rounded up to row-blocks of 16 such that
+// the row-blocks split evenly over the four waves (see Split); with `whole`,
+// to a multiple of four row-blocks, so that no wave has leftover tiles.
+constexpr int padN(int h, int cb, bool whole) {
+  int p = roundup(h, whole ? 64 : 16);
+  while ((((p / 16) % 4) * cb) % 4) p += 16;
   return p;
 }
 
@@ -47,16 +49,19 @@ template <class Op_, int CB_, int H1_, int H2_, int H3_> struct Cfg {
   static constexpr int NQ1 = (32 + KS - 1) / KS;    // layer-1 k-steps (inputs <= 32)
   static constexpr int SC = KS > 64 ? KS : 64;      // layer-1 rows per super-chunk
   static constexpr int H1P = roundup(H1_, SC);
-  static constexpr int H2P = padH(H2_, KS, CB_);
-  static constexpr int H3P = padH(H3_, KS, CB_);
-  static constexpr int R1 = H1P / 16, R2 = H2P / 16, R3 = H3P / 16, R4 = 2;
+  // layers 2 and 3 compute H2N / H3N rows; as the next layer's input they
+  // are zero-padded to whole k-steps (H2P / H3P)
+  // FP8 fragments take twice the registers: no leftover tiles there
+  static constexpr int H2N = padN(H2_, CB_, FRAG == 32), H3N = padN(H3_, CB_, FRAG == 32);
+  static constexpr int H2P = roundup(H2N, KS), H3P = roundup(H3N, KS);
+  static constexpr int R1 = H1P / 16, R2 = H2N / 16, R3 = H3N / 16, R4 = 2;
   static constexpr int NQ2 = H1P / KS, NQ3 = H2P / KS, NQ4 = H3P / KS;
   static constexpr int NSC = H1P / SC, RB1W = SC / 64, QSC = SC / KS, RPQ = KS / 16;
   using S2 = Split<R2, CB_>;
   using S3 = Split<R3, CB_>;
   static constexpr int QBYTES = CB * 64 * FRAG;     // one k-step of a tile's activations
   static constexpr int NW1 = RB1W * NQ1;             // layer-1 fragments per wave per chunk
-  static constexpr int NBIAS = H1P + H2P + H3P + 32; // biases of all layers, FP32
+  static constexpr int NBIAS = H1P + H2N + H3N + 32; // biases of all layers, FP32
   static constexpr int LDS_BIAS = 0;
   static constexpr int LDS_DC = roundup(NBIAS * 4, 16);          // DConst block (FP64)
   static constexpr int LDS_FC = LDS_DC + DConst::N * 8;          // FConst block (FP32)
@@ -66,7 +71,11 @@ template <class Op_, int CB_, int H1_, int H2_, int H3_> struct Cfg {
   static constexpr int NW2 = S2::F + S2::NREM;               // layer-2 fragments per wave per k-step
   static constexpr int NB2 = QSC % 2 == 0 ? 2 : 1;           // layer-2 register buffers
   static constexpr int A2_BYTES = Max<NQ3, NQ4>::v * QBYTES;
-  static constexpr int LDS_BYTES = LDS_A2 + A2_BYTES;
+  // output-layer weights are copied to LDS once per workgroup when they fit
+  static constexpr int W4_BYTES = R4 * NQ4 * 64 * FRAG;
+  static constexpr int LDS_W4 = LDS_A2 + A2_BYTES;
+  static constexpr bool W4_LDS = LDS_W4 + W4_BYTES <= 160 * 1024;
+  static constexpr int LDS_BYTES = LDS_W4 + (W4_LDS ? W4_BYTES : 0);
   static_assert(LDS_BYTES <= 160 * 1024, "LDS budget");
 };
 
@@ -82,6 +91,16 @@ __device__ __forceinline__ void lds_barrier() {
 template <class frag_t>
 __device__ __forceinline__ frag_t ldg_frag(gptr base, int idx, int lane) {
   gptr blk = base + (size_t)idx * (64 * sizeof(frag_t));
+  return *(const __attribute__((address_space(1))) frag_t *)(blk + (uint32_t)(lane * sizeof(frag_t)));
+}
+// The same load, kept at its place in the program: the block address passes
+// through an empty volatile asm statement, which the optimisers neither move
+// across the scheduling barriers nor see through, so the load can not be
+// hoisted ahead of the matrix products it is meant to follow.
+template <class frag_t>
+__device__ __forceinline__ frag_t ldg_frag_here(gptr base, int idx, int lane) {
+  gptr blk = base + (size_t)idx * (64 * sizeof(frag_t));
+  asm volatile("" : "+s"(blk));
   return *(const __attribute__((address_space(1))) frag_t *)(blk + (uint32_t)(lane * sizeof(frag_t)));
 }
 template <class frag_t>
@@ -123,18 +142,37 @@ __global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
   // weight-streaming loops besides the direct-to-LDS copies
   float *const Bl = (float *)(smem + C::LDS_BIAS);
   for (int i = threadIdx.x; i < C::NBIAS; i += blockDim.x) {
-    const int l = i < C::H1P ? 0 : i < C::H1P + C::H2P ? 1 : i < C::H1P + C::H2P + C::H3P ? 2 : 3;
-    const int o = l == 0 ? 0 : l == 1 ? C::H1P : l == 2 ? C::H1P + C::H2P : C::H1P + C::H2P + C::H3P;
+    const int l = i < C::H1P ? 0 : i < C::H1P + C::H2N ? 1 : i < C::H1P + C::H2N + C::H3N ? 2 : 3;
+    const int o = l == 0 ? 0 : l == 1 ? C::H1P : l == 2 ? C::H1P + C::H2N : C::H1P + C::H2N + C::H3N;
     Bl[i] = a.b[l][i - o];
   }
-  const float *const B1 = Bl, *const B2 = Bl + C::H1P, *const B3 = Bl + C::H1P + C::H2P;
-  const float *const B4 = Bl + C::H1P + C::H2P + C::H3P;
+  const float *const B1 = Bl, *const B2 = Bl + C::H1P, *const B3 = Bl + C::H1P + C::H2N;
+  const float *const B4 = Bl + C::H1P + C::H2N + C::H3N;
   // transform and thermodynamic constants too
   double *const dcl = (double *)(smem + C::LDS_DC);
   float *const fcl = (float *)(smem + C::LDS_FC);
   for (int i = threadIdx.x; i < DConst::N; i += blockDim.x) dcl[i] = a.dc[i];
   for (int i = threadIdx.x; i < FConst::N; i += blockDim.x) fcl[i] = a.fc[i];
+  if constexpr (C::W4_LDS)
+    for (int i = threadIdx.x; i < C::W4_BYTES / 16; i += blockDim.x)
+      ((i4 *)(smem + C::LDS_W4))[i] = ((const i4 *)W4g)[i];
   __syncthreads();
+
+  // The preprocess state is loaded one tile ahead: lane (cell 16w + cl,
+  // group g) holds input features f = 16h + 4g + r (T, P, Y_(f-2)), as
+  // xin[4h + r], from clamped (always valid) addresses.
+  double xin[8];
+  auto load_xin = [&](int64_t t) {
+    const int64_t i = t * C::MC + 16 * w + cl;
+    const int64_t ii = (t < a.ntiles && i < a.n) ? i : 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int f = 16 * (j >> 2) + 4 * g + (j & 3);
+      const int s = f - 2 < a.S ? f - 2 : a.S - 1;
+      xin[j] = __builtin_nontemporal_load(f == 0 ? &a.T[ii] : f == 1 ? &a.P[ii] : &a.Y[(int64_t)(s > 0 ? s : 0) * a.ld + ii]);
+    }
+  };
+  if (CB == 4 || w < CB) load_xin(blockIdx.x);
 
   for (int64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
     const int64_t cell0 = tile * C::MC;
@@ -146,18 +184,9 @@ __global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
 
     // ------------------------------------------------------------ preprocess
     // Lane (cell 16w + cl, group g) computes input features f = 16h + 4g + r.
-    if (w < CB) {
+    if (CB == 4 || w < CB) {
       const int64_t i = cell0 + 16 * w + cl;
       const bool valid = i < a.n;
-      const int64_t ii = valid ? i : 0;
-      // all loads first (one latency), then the arithmetic
-      double xin[8];
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int f = 16 * (j >> 2) + 4 * g + (j & 3);
-        const int s = f - 2 < a.S ? f - 2 : a.S - 1;
-        xin[j] = __builtin_nontemporal_load(f == 0 ? &a.T[ii] : f == 1 ? &a.P[ii] : &a.Y[(int64_t)(s > 0 ? s : 0) * a.ld + ii]);
-      }
       f4 v[2];
 #pragma unroll
       for (int h = 0; h < 2; ++h)
@@ -193,37 +222,52 @@ __global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
     __syncthreads();
 
 
-    // Layer 1, super-chunk sc, into A1 buffer `buf`, from this wave's
-    // layer-1 weight fragments of that chunk.
-    auto layer1 = [&](int sc, int buf, const frag_t (&w1f)[C::NW1]) {
+    // Layer 1, super-chunk sc: the products (into acc1) and the activation
+    // (bias + GELU + quantise into A1 buffer `buf`) are separate steps, so
+    // that the activation work can be spread between the layer-2 products.
+    // Value v of the chunk is output value v % 4 of tile (v / 4): row-block
+    // v / (4 CB) of this wave, cell-block (v / 4) % CB.
+    constexpr int NV1 = C::RB1W * CB * 4;              // activation values per lane per chunk
+    f4 acc1[C::RB1W][CB];
+    f4 y1[C::RB1W][CB];
+    auto layer1_mma = [&](int sc, const frag_t (&w1f)[C::NW1]) {
+      // the input fragments, re-read per chunk (cheaper than keeping them
+      // live through the layer-2 loop)
+      frag_t a0[C::NQ1][CB];
+#pragma unroll
+      for (int q = 0; q < C::NQ1; ++q)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) a0[q][cb] = lds_frag<frag_t>(A0, q * CB + cb, lane);
 #pragma unroll
       for (int ii = 0; ii < C::RB1W; ++ii) {
-        const int rbl = w * C::RB1W + ii;              // row-block within the chunk
-        const int rb = sc * (C::SC / 16) + rbl;
-        const frag_t *wf = w1f + ii * C::NQ1;
-        const f4 bias = *(const f4 *)(B1 + 16 * rb + 4 * g);
-        frag_t a0[C::NQ1][CB];            // re-read per chunk: cheaper than 16 live registers
-#pragma unroll
-        for (int q = 0; q < C::NQ1; ++q)
-#pragma unroll
-          for (int cb = 0; cb < CB; ++cb) a0[q][cb] = lds_frag<frag_t>(A0, q * CB + cb, lane);
-        uint8_t *dst = A1 + buf * C::QSC * C::QBYTES;
-        const int q2l = rbl / RPQ, j0 = 4 * (rbl % RPQ);
+        const f4 bias = *(const f4 *)(B1 + 16 * (sc * (C::SC / 16) + w * C::RB1W + ii) + 4 * g);
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) {
-          f4 acc = Op::SCALED ? f4{0.f, 0.f, 0.f, 0.f} : bias;
+          acc1[ii][cb] = Op::SCALED ? f4{0.f, 0.f, 0.f, 0.f} : bias;
 #pragma unroll
-          for (int q = 0; q < C::NQ1; ++q) acc = Op::mma(wf[q], a0[q][cb], acc);
-          f4 y;
+          for (int q = 0; q < C::NQ1; ++q) acc1[ii][cb] = Op::mma(w1f[ii * C::NQ1 + q], a0[q][cb], acc1[ii][cb]);
+        }
+      }
+    };
+    // activation values [v0, v1) of chunk sc; a tile is stored with its last value
+    auto layer1_act = [&](int sc, int buf, int v0, int v1) {
+      uint8_t *dst = A1 + buf * C::QSC * C::QBYTES;
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            float zz = Op::SCALED ? __builtin_fmaf(acc[r], sout[0], bias[r]) : acc[r];
-            y[r] = gelu(zz);
-          }
+      for (int v = 0; v < NV1; ++v) {
+        if (v < v0 || v >= v1) continue;
+        const int ii = v / (4 * CB), cb = (v / 4) % CB, r = v % 4;
+        const int rbl = w * C::RB1W + ii;              // row-block within the chunk
+        const int rb = sc * (C::SC / 16) + rbl;
+        const float bias = B1[16 * rb + 4 * g + r];
+        const float zz = Op::SCALED ? __builtin_fmaf(acc1[ii][cb][r], sout[0], bias) : acc1[ii][cb][r];
+        y1[ii][cb][r] = gelu(zz);
+        if (r == 3) {
+          f4 y = y1[ii][cb];
           if (CALIB && cell0 + 16 * cb + cl < a.n)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) amx[1] = umaxf(amx[1], __builtin_fabsf(y[r]));
+            for (int k = 0; k < 4; ++k) amx[1] = umaxf(amx[1], __builtin_fabsf(y[k]));
           if (Op::SCALED) y *= inv_sa[1];
+          const int q2l = rbl / RPQ, j0 = 4 * (rbl % RPQ);
           Op::store4(dst + ((q2l * CB + cb) * 64 + lane) * FRAG + j0 * EB, y);
         }
       }
@@ -268,7 +312,8 @@ __global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
         }
     };
     w1_load(0);
-    layer1(0, 0, w1r);
+    layer1_mma(0, w1r);
+    layer1_act(0, 0, 0, NV1);
     w1_load(1);
 #pragma unroll
     for (int b = 0; b < NB2; ++b)
@@ -278,12 +323,17 @@ __global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
 
 #pragma nounroll
     for (int sc = 0; sc < C::NSC; ++sc) {
-      // layer 1 of the next chunk (the last iteration recomputes chunk 0 into
-      // the idle buffer, which keeps the loop body uniform) follows the first
-      // k-step's matrix products in program order, so its activation
-      // arithmetic can issue while those products execute
+      // The next chunk's layer-1 products go first (their operands are in
+      // registers and LDS already; the last iteration recomputes chunk 0 into
+      // the idle buffer, which keeps the loop body uniform).  Their activation
+      // values are then spread over the layer-2 fragment groups, NPG values
+      // per group from group G0 on, so that the activation arithmetic issues
+      // while the matrix products execute.
       const int nsc = (sc + 1 == C::NSC) ? 0 : sc + 1;
+      const int nbuf = (sc + 1) & 1;
       const uint8_t *src = A1 + (sc & 1) * C::QSC * C::QBYTES;
+      layer1_mma(nsc, w1r);
+      w1_load(sc + 2);
       // the chunk's activation fragments, read once
       frag_t act[C::QSC][NA2];
 #pragma unroll
@@ -293,6 +343,9 @@ __global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
 #pragma unroll
         for (int k = 0; k < S2::NREM; ++k) act[ql][CB + k] = lds_frag<frag_t>(src, ql * CB + S2::rem_cb(w, k), lane);
       }
+      constexpr int NGR = C::QSC * NW2;                // fragment groups per chunk
+      constexpr int G0 = NGR > 4 ? 2 : 0;
+      constexpr int NPG = (NV1 + (NGR - G0) - 1) / (NGR - G0);
 #pragma unroll
       for (int ql = 0; ql < C::QSC; ++ql) {
         const int q = sc * C::QSC + ql;
@@ -301,30 +354,58 @@ __global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
         // that read the fragment (the scheduler would otherwise sink the
         // loads towards their next use and shorten their lead)
 #pragma unroll
-        for (int i = 0; i < S2::F; ++i) {
+        for (int i = 0; i < NW2; ++i) {
+          if (i < S2::F) {
 #pragma unroll
-          for (int cb = 0; cb < CB; ++cb) acc2[i * CB + cb] = Op::mma(wc[i], act[ql][cb], acc2[i * CB + cb]);
+            for (int cb = 0; cb < CB; ++cb) acc2[i * CB + cb] = Op::mma(wc[i], act[ql][cb], acc2[i * CB + cb]);
+          } else {
+            const int k = i - S2::F;
+            acc2[S2::F * CB + k] = Op::mma(wc[i], act[ql][CB + k], acc2[S2::F * CB + k]);
+          }
           w2_load(wc[i], i, q + NB2);
-          __builtin_amdgcn_sched_barrier(0);
+          const int gi = ql * NW2 + i;
+          if (gi >= G0) layer1_act(nsc, nbuf, (gi - G0) * NPG, (gi - G0 + 1) * NPG);
         }
+        // Instruction order of the k-step, per fragment group: each matrix
+        // product followed by up to three activation instructions (VALU or
+        // transcendental), then the group's refill load.  The activation work
+        // then issues while the products execute.
 #pragma unroll
-        for (int k = 0; k < S2::NREM; ++k) {
-          acc2[S2::F * CB + k] = Op::mma(wc[S2::F + k], act[ql][CB + k], acc2[S2::F * CB + k]);
-          w2_load(wc[S2::F + k], S2::F + k, q + NB2);
-          __builtin_amdgcn_sched_barrier(0);
+        for (int i = 0; i < NW2; ++i) {
+#pragma unroll
+          for (int m = 0; m < (i < S2::F ? CB : 1); ++m) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x402, 3, 0);
+          }
+          __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
         }
-        if (ql == 0) {
-          layer1(nsc, (sc + 1) & 1, w1r);
-          w1_load(sc + 2);
-        }
+        __builtin_amdgcn_sched_barrier(0);
       }
       lds_barrier();
     }
     __syncthreads();
 
+    // The first k-step of layer-3 weights is requested now, so its latency
+    // overlaps the layer-2 activation phase; the next ones follow it.
+    constexpr int NW3 = S3::F + S3::NREM;              // fragments per wave per k-step
+    constexpr int NB3 = FRAG == 32 ? 1 : 3;            // k-steps in flight (FP8 k-steps are 4x longer)
+    constexpr int NA3 = CB + (S3::NREM > 0 ? S3::NREM : 1);
+    frag_t w3b[NB3][NW3];
+    auto w3_load = [&](frag_t &dst, int i, int q) {
+      const int rb = i < S3::F ? w * S3::F + i : S3::rem_rb(w, i - S3::F);
+      dst = ldg_frag<frag_t>(W3, rb * C::NQ3 + q, lane);
+    };
+#pragma unroll
+    for (int i = 0; i < NW3; ++i) w3_load(w3b[0][i], i, 0);
+
     // layer-2 activation -> LDS (layer-3 B fragments)
     auto put = [&](uint8_t *base, int rb, int cb, f4 y) {
       Op::store4(base + (((rb / RPQ) * CB + cb) * 64 + lane) * FRAG + 4 * (rb % RPQ) * EB, y);
+    };
+    // rows past the computed ones, up to the next k-step boundary, are zero
+    auto zero_pad = [&](int r0, int r1) {
+#pragma unroll
+      for (int t = w; t < (r1 - r0) * CB; t += 4) put(A2, r0 + t / CB, t % CB, f4{0.f, 0.f, 0.f, 0.f});
     };
     {
 #pragma unroll
@@ -341,7 +422,12 @@ __global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
           for (int r = 0; r < 4; ++r) amx[2] = umaxf(amx[2], __builtin_fabsf(y[r]));
         if (Op::SCALED) y *= inv_sa[2];
         put(A2, rb, cb, y);
+        // FP8: two tiles at a time, which keeps the accumulators where they
+        // are instead of letting the scheduler copy them all out of the
+        // accumulation registers up front (the register file is full there)
+        if (FRAG == 32 && (t & 1)) __builtin_amdgcn_sched_barrier(0);
       }
+      zero_pad(C::R2, C::H2P / 16);
     }
     __syncthreads();
 
@@ -359,43 +445,65 @@ __global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
       acc3[S3::F * CB + k] = Op::SCALED ? f4{0.f, 0.f, 0.f, 0.f}
                                         : *(const f4 *)(B3 + 16 * S3::rem_rb(w, k) + 4 * g);
     {
-      // fully unrolled: every load index is a constant, so the compiler's
-      // wait counts are exact; weights are fetched three k-steps ahead into a
-      // four-deep register ring and activations one k-step ahead
-      constexpr int NW3 = S3::F + S3::NREM;
-      constexpr int PD = 3;                            // weight prefetch distance
-      frag_t w3r[PD + 1][NW3];
-      auto load_w3 = [&](frag_t (&dst)[NW3], int q) {
-#pragma unroll
-        for (int i = 0; i < S3::F; ++i) dst[i] = ldg_frag<frag_t>(W3, (w * S3::F + i) * C::NQ3 + q, lane);
-#pragma unroll
-        for (int k = 0; k < S3::NREM; ++k)
-          dst[S3::F + k] = ldg_frag<frag_t>(W3, S3::rem_rb(w, k) * C::NQ3 + q, lane);
-      };
-      frag_t a3r[2][CB + (S3::NREM > 0 ? S3::NREM : 1)];
-      auto load_a3 = [&](frag_t (&dst)[CB + (S3::NREM > 0 ? S3::NREM : 1)], int q) {
+      // Fully unrolled: every load index is a constant, so the compiler's
+      // wait counts are exact.  Fragment i of k-step q + NB3 is loaded as
+      // soon as the products of k-step q have read fragment i; activations
+      // are read one k-step ahead.
+      frag_t a3r[2][NA3];
+      auto load_a3 = [&](frag_t (&dst)[NA3], int q) {
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) dst[cb] = lds_frag<frag_t>(A2, q * CB + cb, lane);
 #pragma unroll
         for (int k = 0; k < S3::NREM; ++k) dst[CB + k] = lds_frag<frag_t>(A2, q * CB + S3::rem_cb(w, k), lane);
       };
+      if constexpr (NB3 == 1) {
+        // one buffer: a rolled loop, one k-step per iteration (a basic block
+        // each, which keeps every refill behind the products of its k-step)
+#pragma nounroll
+        for (int q = 0; q < C::NQ3; ++q) {
+          frag_t ac[NA3];
+          load_a3(ac, q);
+          const int qn = q + 1 < C::NQ3 ? q + 1 : q;
 #pragma unroll
-      for (int q = 0; q < PD; ++q)
-        if (q < C::NQ3) load_w3(w3r[q], q);
-      load_a3(a3r[0], 0);
+          for (int i = 0; i < S3::F; ++i) {
 #pragma unroll
-      for (int q = 0; q < C::NQ3; ++q) {
-        if (q + PD < C::NQ3) load_w3(w3r[(q + PD) % (PD + 1)], q + PD);
-        if (q + 1 < C::NQ3) load_a3(a3r[(q + 1) & 1], q + 1);
-        const frag_t(&wc3)[NW3] = w3r[q % (PD + 1)];
-        const auto &ac = a3r[q & 1];
+            for (int cb = 0; cb < CB; ++cb) acc3[i * CB + cb] = Op::mma(w3b[0][i], ac[cb], acc3[i * CB + cb]);
+            w3_load(w3b[0][i], i, qn);
+            __builtin_amdgcn_sched_barrier(0);
+          }
 #pragma unroll
-        for (int i = 0; i < S3::F; ++i)
+          for (int k = 0; k < S3::NREM; ++k) {
+            acc3[S3::F * CB + k] = Op::mma(w3b[0][S3::F + k], ac[CB + k], acc3[S3::F * CB + k]);
+            w3_load(w3b[0][S3::F + k], S3::F + k, qn);
+            __builtin_amdgcn_sched_barrier(0);
+          }
+        }
+      } else {
 #pragma unroll
-          for (int cb = 0; cb < CB; ++cb) acc3[i * CB + cb] = Op::mma(wc3[i], ac[cb], acc3[i * CB + cb]);
+        for (int b = 1; b < NB3; ++b)
 #pragma unroll
-        for (int k = 0; k < S3::NREM; ++k)
-          acc3[S3::F * CB + k] = Op::mma(wc3[S3::F + k], ac[CB + k], acc3[S3::F * CB + k]);
+          for (int i = 0; i < NW3; ++i)
+            if (b < C::NQ3) w3_load(w3b[b][i], i, b);
+        load_a3(a3r[0], 0);
+#pragma unroll
+        for (int q = 0; q < C::NQ3; ++q) {
+          if (q + 1 < C::NQ3) load_a3(a3r[(q + 1) & 1], q + 1);
+          frag_t(&wc)[NW3] = w3b[q % NB3];
+          const auto &ac = a3r[q & 1];
+#pragma unroll
+          for (int i = 0; i < S3::F; ++i) {
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) acc3[i * CB + cb] = Op::mma(wc[i], ac[cb], acc3[i * CB + cb]);
+            if (q + NB3 < C::NQ3) w3_load(wc[i], i, q + NB3);
+            __builtin_amdgcn_sched_barrier(0);
+          }
+#pragma unroll
+          for (int k = 0; k < S3::NREM; ++k) {
+            acc3[S3::F * CB + k] = Op::mma(wc[S3::F + k], ac[CB + k], acc3[S3::F * CB + k]);
+            if (q + NB3 < C::NQ3) w3_load(wc[S3::F + k], S3::F + k, q + NB3);
+            __builtin_amdgcn_sched_barrier(0);
+          }
+        }
       }
     }
     // The state of the post-processing is fetched now, so its latency
@@ -404,13 +512,17 @@ __global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
     const int64_t ipost = cell0 + 16 * w + cl;
     const bool vpost = ipost < a.n;
     const int64_t icp = vpost ? ipost : 0;
-    if (!CALIB && w < CB) {
+    if (CB == 4 || w < CB) load_xin(tile + gridDim.x);
+    if (!CALIB && (CB == 4 || w < CB)) {
+      // unconditional loads from clamped, valid addresses: no branches
       Tc = __builtin_nontemporal_load(&a.T[icp]);
       Pc = __builtin_nontemporal_load(&a.P[icp]);
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         const int s = 16 * (j >> 2) + 4 * g + (j & 3) - 2;
-        Yc[j] = (s >= 0 && s < a.S) ? __builtin_nontemporal_load(&a.Y[(int64_t)s * a.ld + icp]) : 0.0;
+        const int sv = s < 0 ? 0 : s < a.S ? s : a.S - 1;
+        const double v = __builtin_nontemporal_load(&a.Y[(int64_t)sv * a.ld + icp]);
+        Yc[j] = (s >= 0 && s < a.S) ? v : 0.0;
       }
     }
     __syncthreads();  // every wave is done reading the layer-2 activation
@@ -429,7 +541,9 @@ __global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
           for (int r = 0; r < 4; ++r) amx[3] = umaxf(amx[3], __builtin_fabsf(y[r]));
         if (Op::SCALED) y *= inv_sa[3];
         put(A2, rb, cb, y);
+        if (FRAG == 32 && (t & 1)) __builtin_amdgcn_sched_barrier(0);
       }
+      zero_pad(C::R3, C::H3P / 16);
     }
     __syncthreads();
     if (CALIB) continue;
@@ -440,17 +554,24 @@ __global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
 #pragma unroll
       for (int rb = 0; rb < 2; ++rb)
         o[rb] = Op::SCALED ? f4{0.f, 0.f, 0.f, 0.f} : *(const f4 *)(B4 + 16 * rb + 4 * g);
-      // all layer-4 fragments in flight at once
-      frag_t w4r[2][C::NQ4];
+      // all layer-4 fragments in flight at once (FP8: one k-step at a time,
+      // its fragments are twice as large)
+      constexpr int NQ4L = FRAG == 32 ? 1 : C::NQ4;
 #pragma unroll
-      for (int rb = 0; rb < 2; ++rb)
+      for (int q0 = 0; q0 < C::NQ4; q0 += NQ4L) {
+        frag_t w4r[2][NQ4L];
 #pragma unroll
-        for (int q = 0; q < C::NQ4; ++q) w4r[rb][q] = ldg_frag<frag_t>(W4, rb * C::NQ4 + q, lane);
+        for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-      for (int q = 0; q < C::NQ4; ++q) {
-        const frag_t af = lds_frag<frag_t>(A2, q * CB + w, lane);
+          for (int q = 0; q < NQ4L; ++q)
+            w4r[rb][q] = C::W4_LDS ? lds_frag<frag_t>(smem + C::LDS_W4, rb * C::NQ4 + q0 + q, lane)
+                                   : ldg_frag<frag_t>(W4, rb * C::NQ4 + q0 + q, lane);
 #pragma unroll
-        for (int rb = 0; rb < 2; ++rb) o[rb] = Op::mma(w4r[rb][q], af, o[rb]);
+        for (int q = 0; q < NQ4L; ++q) {
+          const frag_t af = lds_frag<frag_t>(A2, (q0 + q) * CB + w, lane);
+#pragma unroll
+          for (int rb = 0; rb < 2; ++rb) o[rb] = Op::mma(w4r[rb][q], af, o[rb]);
+        }
       }
       if (Op::SCALED)
 #pragma unroll
@@ -610,6 +731,7 @@ bool find_layout(int p, int h1, int h2, int h3, NetLayout *out) {
       case P_FP32: fill_layout<Cfg<OpF32, 2, H1, H2, H3>, true>(out); return true;    \
       case P_BF16: fill_layout<Cfg<OpBF16, 4, H1, H2, H3>, false>(out); return true;  \
       case P_FP16: fill_layout<Cfg<OpF16, 4, H1, H2, H3>, false>(out); return true;   \
+      case P_FP8: fill_layout<Cfg<OpF8, 4, H1, H2, H3>, false>(out); return true;     \
       default: return false;                                                          \
     }                                                                                 \
   }

@@ -111,6 +111,62 @@ def test_large_net_narrow_matches_emulation(prec, fmt):
     assert np.abs(tg).max() <= np.abs(te).max()
 
 
+def _fp8_setup(config, n_cal=1 << 14):
+    """Net and its FP8 scales from the oracle: per-layer input amax of the
+    exact forward over a separate calibration draw, weight amax, and the
+    power-of-two scales of both.  The amax goes to the GPU as an input."""
+    net = synth.make_net(config)
+    cal = synth.make_state(config, n_cal, stream="calibration")
+    amax = chem.layer_input_amax(cal.T, cal.P, cal.Y, net).astype(np.float32)
+    act_s = chem.pow2_scale(amax.astype(np.float64))
+    w_s = chem.pow2_scale(chem.weight_amax(net))
+    return net, amax, act_s, w_s
+
+
+@pytest.mark.parametrize("config", [1, 2])
+def test_fp8_scales_match_oracle(config):
+    """The library's power-of-two activation and weight scales equal the
+    oracle's, bit for bit."""
+    _note(f"case fp8 scales config={config}")
+    net, amax, act_s, w_s = _fp8_setup(config)
+    h = make_handle(net, "fp8", act_amax=amax)
+    a, w = h.scales()
+    np.testing.assert_array_equal(a.astype(np.float64), act_s)
+    np.testing.assert_array_equal(w.astype(np.float64), w_s)
+
+
+@pytest.mark.parametrize("config,n", [(1, 4096 - 5), (2, 4096 + 11)])
+def test_fp8_matches_emulation(config, n):
+    """FP8 e4m3 operands with per-layer scales against the oracle that rounds
+    the same scaled operands; same statistical bar as the 16-bit formats
+    (a rounding flip is rarer but larger in e4m3)."""
+    _note(f"case fp8 config={config} n={n}")
+    net, amax, act_s, w_s = _fp8_setup(config)
+    S = 17 if config == 1 else 29
+    thermo = synth.make_thermo(config, S)
+    st = synth.make_state(config, n)
+    h = make_handle(net, "fp8", thermo=thermo, act_amax=amax)
+    Yg, Tg, nbad = _run(h, st)
+    assert nbad == 0
+    emu = chem.step(st.T, st.P, st.Y, net, fmt="e4m3", act_scale=act_s, w_scale=w_s, thermo=thermo)
+    ex = chem.step(st.T, st.P, st.Y, net, thermo=thermo)
+    ge, ee = Yg - emu["Y_new"], emu["Y_new"] - ex["Y_new"]
+    rg, re = _rel(Yg, emu["Y_new"]), _rel(emu["Y_new"], ex["Y_new"])
+    rms_g, rms_e = np.sqrt(np.mean(ge ** 2)), np.sqrt(np.mean(ee ** 2))
+    _note(f"  gpu-emu: rms {rms_g:.2e} med {np.median(rg):.2e} p99 {np.quantile(rg, .99):.2e} "
+          f"max {rg.max():.2e} | emu-fp64: rms {rms_e:.2e} med {np.median(re):.2e} "
+          f"p99 {np.quantile(re, .99):.2e} max {re.max():.2e} | gpu-fp64 max abs dY "
+          f"{np.abs(Yg - ex['Y_new']).max():.2e} T {np.abs(Tg - ex['T_new']).max():.2e} K")
+    assert rms_g <= 0.25 * rms_e
+    assert np.median(rg) <= 0.05 * np.median(re)
+    assert np.quantile(rg, 0.99) <= 0.5 * np.quantile(re, 0.99)
+    assert rg.max() <= 0.5 * re.max()
+    tg, te = Tg - emu["T_new"], emu["T_new"] - ex["T_new"]
+    assert np.sqrt(np.mean(tg ** 2)) <= 0.25 * np.sqrt(np.mean(te ** 2))
+    assert np.abs(tg).max() <= np.abs(te).max()
+    np.testing.assert_allclose(Yg.sum(axis=0), 1.0, atol=1e-13)
+
+
 # ------------------------------------------------------------------ properties
 def test_cells_are_independent_and_runs_deterministic():
     _note("case independence bf16")
