@@ -222,11 +222,10 @@ __global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
     __syncthreads();
 
 
-    // Layer 1, super-chunk sc: the products (into acc1) and the activation
-    // (bias + GELU + quantise into A1 buffer `buf`) are separate steps, so
-    // that the activation work can be spread between the layer-2 products.
-    // Value v of the chunk is output value v % 4 of tile (v / 4): row-block
-    // v / (4 CB) of this wave, cell-block (v / 4) % CB.
+    // Layer 1, super-chunk sc, in two steps: the products (into acc1) and the
+    // activation of values [v0, v1) (bias + GELU + quantise into A1 buffer
+    // `buf`).  Value v of the chunk is output value v % 4 of tile v / 4:
+    // row-block v / (4 CB) of this wave, cell-block (v / 4) % CB.
     constexpr int NV1 = C::RB1W * CB * 4;              // activation values per lane per chunk
     f4 acc1[C::RB1W][CB];
     f4 y1[C::RB1W][CB];
@@ -323,17 +322,13 @@ __global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
 
 #pragma nounroll
     for (int sc = 0; sc < C::NSC; ++sc) {
-      // The next chunk's layer-1 products go first (their operands are in
-      // registers and LDS already; the last iteration recomputes chunk 0 into
-      // the idle buffer, which keeps the loop body uniform).  Their activation
-      // values are then spread over the layer-2 fragment groups, NPG values
-      // per group from group G0 on, so that the activation arithmetic issues
-      // while the matrix products execute.
+      // Layer 1 of the next chunk follows the first fragment group's products
+      // (the last iteration recomputes chunk 0 into the idle buffer, which
+      // keeps the loop body uniform).  Measured: one block there is faster
+      // than spreading its activation values over the fragment groups.
       const int nsc = (sc + 1 == C::NSC) ? 0 : sc + 1;
       const int nbuf = (sc + 1) & 1;
       const uint8_t *src = A1 + (sc & 1) * C::QSC * C::QBYTES;
-      layer1_mma(nsc, w1r);
-      w1_load(sc + 2);
       // the chunk's activation fragments, read once
       frag_t act[C::QSC][NA2];
 #pragma unroll
@@ -343,9 +338,6 @@ __global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
 #pragma unroll
         for (int k = 0; k < S2::NREM; ++k) act[ql][CB + k] = lds_frag<frag_t>(src, ql * CB + S2::rem_cb(w, k), lane);
       }
-      constexpr int NGR = C::QSC * NW2;                // fragment groups per chunk
-      constexpr int G0 = NGR > 4 ? 2 : 0;
-      constexpr int NPG = (NV1 + (NGR - G0) - 1) / (NGR - G0);
 #pragma unroll
       for (int ql = 0; ql < C::QSC; ++ql) {
         const int q = sc * C::QSC + ql;
@@ -363,23 +355,13 @@ __global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
             acc2[S2::F * CB + k] = Op::mma(wc[i], act[ql][CB + k], acc2[S2::F * CB + k]);
           }
           w2_load(wc[i], i, q + NB2);
-          const int gi = ql * NW2 + i;
-          if (gi >= G0) layer1_act(nsc, nbuf, (gi - G0) * NPG, (gi - G0 + 1) * NPG);
-        }
-        // Instruction order of the k-step, per fragment group: each matrix
-        // product followed by up to three activation instructions (VALU or
-        // transcendental), then the group's refill load.  The activation work
-        // then issues while the products execute.
-#pragma unroll
-        for (int i = 0; i < NW2; ++i) {
-#pragma unroll
-          for (int m = 0; m < (i < S2::F ? CB : 1); ++m) {
-            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-            __builtin_amdgcn_sched_group_barrier(0x402, 3, 0);
+          if (ql == 0 && i == 0) {
+            layer1_mma(nsc, w1r);
+            w1_load(sc + 2);
+            layer1_act(nsc, nbuf, 0, NV1);
           }
-          __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+          __builtin_amdgcn_sched_barrier(0);
         }
-        __builtin_amdgcn_sched_barrier(0);
       }
       lds_barrier();
     }
@@ -731,7 +713,7 @@ bool find_layout(int p, int h1, int h2, int h3, NetLayout *out) {
       case P_FP32: fill_layout<Cfg<OpF32, 2, H1, H2, H3>, true>(out); return true;    \
       case P_BF16: fill_layout<Cfg<OpBF16, 4, H1, H2, H3>, false>(out); return true;  \
       case P_FP16: fill_layout<Cfg<OpF16, 4, H1, H2, H3>, false>(out); return true;   \
-      case P_FP8: fill_layout<Cfg<OpF8, 4, H1, H2, H3>, false>(out); return true;     \
+      case P_FP8: fill_layout<Cfg<OpF8, 3, H1, H2, H3>, false>(out); return true;     \
       default: return false;                                                          \
     }                                                                                 \
   }
