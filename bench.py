@@ -63,6 +63,8 @@ def main():
     ap.add_argument("--cells", type=int, default=1 << 20)
     ap.add_argument("--precisions", default="fp32,bf16,fp16,fp8")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline leg")
+    ap.add_argument("--workloads", default="fp8_bimodal_2p24,block_2p27,train_b65536",
+                    help="further workloads timed after the headline one ('' for none)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="bytes of one plain device copy run before the timed region")
     ap.add_argument("--traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -162,9 +164,17 @@ def main():
     achieved = FLOP_PER_CELL * n / (kern_ms * 1e-3) * 1e-12
     traffic = stored_traffic(n)
 
+    # the headline state is no longer needed on the device
+    del T, P, Y, Yo, To
+    torch.cuda.empty_cache()
+    extra = {}
+    sampled = {}
+    for wl in [w for w in args.workloads.split(",") if w]:
+        extra[wl], sampled[wl] = WORKLOADS[wl](torch, synth, ChemDNN)
+
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(st, net, thermo, sample, outputs, results)
+        cpu = cpu_baseline(st, net, thermo, sample, outputs, results, sampled, extra)
 
     line = {
         "metric": "DNN-chemistry cells/s (BF16 MFMA operands, FP32 accumulate, FP64 update)",
@@ -189,9 +199,147 @@ def main():
                      "flop_per_cell": FLOP_PER_CELL,
                      "state_GBps": STATE_BYTES_PER_CELL * n / (kern_ms * 1e-3) * 1e-9},
         "precisions": results,
+        "workloads": extra,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def _time_steps(torch, h, T, P, Y, Yo, To, steps, warmup):
+    for _ in range(warmup):
+        h.step(T, P, Y, Y_out=Yo, T_out=To)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        h.step(T, P, Y, Y_out=Yo, T_out=To)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def _rate(n, ms, prec):
+    tf = FLOP_PER_CELL * n / (ms * 1e-3) * 1e-12
+    return {"ms_per_step": ms, "cells_per_s": n / (ms * 1e-3), "tflops": tf,
+            "mfma_frac": tf / PEAK_TFLOPS[prec],
+            "state_GBps": STATE_BYTES_PER_CELL * n / (ms * 1e-3) * 1e-9}
+
+
+def _fp8_amax(torch, ChemDNN, net, thermo, T, P, Y):
+    """Per-layer input amax from the library's FP32 calibration pass."""
+    params = torch.tensor(net.flat_params(), device="cuda")
+    h = ChemDNN(net.widths, "fp32", params, net.in_mean, net.in_std, net.out_mean, net.out_std,
+                thermo=thermo, lam=net.lam)
+    amax = h.calibrate(T, P, Y).cpu().numpy()
+    h.close()
+    return amax
+
+
+def wl_fp8_bimodal(torch, synth, ChemDNN, n=1 << 24):
+    """FP8 e4m3 over 2^24 cells with bimodal T (N(800,100) | N(2800,150) K),
+    scales from a 2^16-cell calibration draw; the FP32 and BF16 paths run on
+    the same batch for comparison."""
+    net = synth.make_net(3)
+    thermo = synth.make_thermo(3, 29)
+    st = synth.make_state(3, n)
+    cal = synth.make_state(3, 1 << 16, stream="calibration")
+    dev = torch.device("cuda")
+    amax = _fp8_amax(torch, ChemDNN, net, thermo, torch.tensor(cal.T, device=dev),
+                     torch.tensor(cal.P, device=dev), torch.tensor(cal.Y, device=dev))
+    idx = synth.subsample_indices(3, n, 1 << 10)
+    T, P, Y = (torch.tensor(a, device=dev) for a in (st.T, st.P, st.Y))
+    idx_t = torch.tensor(idx, device=dev)
+    Yo, To = torch.empty_like(Y), torch.empty_like(T)
+    params = torch.tensor(net.flat_params(), device=dev)
+    out, samp = {}, {"state": (st.T[idx], st.P[idx], st.Y[:, idx]), "net": net, "thermo": thermo}
+    for prec in ("fp8", "bf16", "fp32"):
+        h = ChemDNN(net.widths, prec, params, net.in_mean, net.in_std, net.out_mean, net.out_std,
+                    act_amax=amax if prec == "fp8" else None, thermo=thermo, lam=net.lam)
+        ms = _time_steps(torch, h, T, P, Y, Yo, To, 3 if prec == "fp32" else 10, 2)
+        h.close()
+        out[prec] = _rate(n, ms, prec)
+        samp[prec] = (Yo[:, idx_t].cpu().numpy(), To[idx_t].cpu().numpy())
+    for prec in ("bf16", "fp32"):
+        out["fp8"][f"max_abs_dY_vs_{prec}"] = float(np.max(np.abs(samp["fp8"][0] - samp[prec][0])))
+        out["fp8"][f"max_abs_dT_K_vs_{prec}"] = float(np.max(np.abs(samp["fp8"][1] - samp[prec][1])))
+    out["config"] = {"cells": n, "T": "bimodal N(800,100) | N(2800,150) K", "P": "lognormal 10 MPa",
+                     "Y": "Dirichlet(0.5)", "calibration_cells": 1 << 16}
+    del T, P, Y, Yo, To
+    torch.cuda.empty_cache()
+    return out, samp
+
+
+def wl_block(torch, synth, ChemDNN, edge=512):
+    """The 512^3 block (seeded smooth fields, LOX/CH4-like compositions), BF16
+    and FP8, state drawn on the device."""
+    n = edge ** 3
+    net = synth.make_net(5)
+    thermo = synth.make_thermo(5, 29)
+    T, P, Y = synth.make_block_state_device(5, edge, 29, device="cuda")
+    dev = torch.device("cuda")
+    cal_t = torch.tensor(synth.subsample_indices(5, n, 1 << 16), device=dev)
+    amax = _fp8_amax(torch, ChemDNN, net, thermo, T[cal_t].contiguous(), P[cal_t].contiguous(),
+                     Y[:, cal_t].contiguous())
+    idx_t = torch.tensor(synth.subsample_indices(5, n, 1 << 10), device=dev)
+    samp = {"state": (T[idx_t].cpu().numpy(), P[idx_t].cpu().numpy(), Y[:, idx_t].cpu().numpy()),
+            "net": net, "thermo": thermo}
+    Yo, To = torch.empty_like(Y), torch.empty_like(T)
+    params = torch.tensor(net.flat_params(), device=dev)
+    out = {}
+    for prec in ("bf16", "fp8"):
+        h = ChemDNN(net.widths, prec, params, net.in_mean, net.in_std, net.out_mean, net.out_std,
+                    act_amax=amax if prec == "fp8" else None, thermo=thermo, lam=net.lam)
+        ms = _time_steps(torch, h, T, P, Y, Yo, To, 3, 1)
+        h.close()
+        out[prec] = _rate(n, ms, prec)
+        samp[prec] = (Yo[:, idx_t].cpu().numpy(), To[idx_t].cpu().numpy())
+    out["config"] = {"cells": n, "block": f"{edge}^3", "T": "300 + 2900 c K", "P": "5 + 15 p MPa",
+                     "Y": "mix of LOX-like / CH4-like compositions and Dirichlet(0.5)"}
+    del T, P, Y, Yo, To
+    torch.cuda.empty_cache()
+    return out, samp
+
+
+def wl_train(torch, synth, ChemDNN, B=65536, steps=20):
+    """One Adam training step of the 19-400-200-100-17 net over a batch of
+    65,536 states (features, FP32 forward with saved pre-activations, MSE,
+    backward, Adam), timed; targets are seeded normal draws (the step's work
+    does not depend on their values)."""
+    net = synth.make_net(4)
+    st = synth.make_state(4, B)
+    dev = torch.device("cuda")
+    T, P, Y = (torch.tensor(a, device=dev) for a in (st.T, st.P, st.Y))
+    rng = synth.streams(4)["extra"]
+    tgt = torch.tensor(rng.standard_normal((17, B)), dtype=torch.float32, device=dev)
+    p = torch.tensor(net.flat_params(), device=dev)
+    g, m, v = torch.empty_like(p), torch.zeros_like(p), torch.zeros_like(p)
+    h = ChemDNN(net.widths, "fp32", p, net.in_mean, net.in_std, net.out_mean, net.out_std,
+                lam=net.lam, max_batch=B)
+    out = {}
+    for recompute in (False, True):
+        for k in range(1, 3):
+            h.train_step(T, P, Y, tgt, p, g, m, v, k, lr=1e-3, recompute=recompute)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for k in range(3, 3 + steps):
+            h.train_step(T, P, Y, tgt, p, g, m, v, k, lr=1e-3, recompute=recompute)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        fl = 3 * 2 * sum(a * b for a, b in zip(net.widths[:-1], net.widths[1:])) * B
+        out["recompute" if recompute else "saved"] = {
+            "ms_per_step": ms, "samples_per_s": B / (ms * 1e-3),
+            "tflops_fwd_bwd": fl / (ms * 1e-3) * 1e-12}
+    h.close()
+    out["config"] = {"batch": B, "widths": list(net.widths), "optimizer": "Adam lr 1e-3",
+                     "targets": "seeded normal draws of the label shape"}
+    return out, None
+
+
+WORKLOADS = {"fp8_bimodal_2p24": wl_fp8_bimodal, "block_2p27": wl_block, "train_b65536": wl_train}
 
 
 def _counter_means(path, name_part):
@@ -231,9 +379,10 @@ def write_traffic(fetch_csv, write_csv, n_cells, copy_bytes):
     print(json.dumps(rec))
 
 
-def cpu_baseline(st, net, thermo, sample, outputs, results):
+def cpu_baseline(st, net, thermo, sample, outputs, results, sampled=None, extra=None):
     """The FP64 oracle on the host cores, on a bounded sample of the same
-    workload; its results are also the reference of the stated errors."""
+    workload; its results are also the reference of the stated errors (of the
+    headline workload and, on their own samples, of the further workloads)."""
     from threadpoolctl import threadpool_info
     from oracle import chem
     idx = np.asarray(sample)
@@ -249,6 +398,17 @@ def cpu_baseline(st, net, thermo, sample, outputs, results):
     for prec, (Yg, Tg) in outputs.items():
         results[prec]["max_abs_dY"] = float(np.max(np.abs(Yg - ref["Y_new"])))
         results[prec]["max_abs_dT_K"] = float(np.max(np.abs(Tg - ref["T_new"])))
+    for wl, sm in (sampled or {}).items():
+        if not sm:
+            continue
+        Tw, Pw, Yw = sm["state"]
+        refw = chem.step(Tw, Pw, Yw, sm["net"], thermo=sm["thermo"])
+        for prec, val in sm.items():
+            if prec in ("state", "net", "thermo"):
+                continue
+            extra[wl][prec]["max_abs_dY"] = float(np.max(np.abs(val[0] - refw["Y_new"])))
+            extra[wl][prec]["max_abs_dT_K"] = float(np.max(np.abs(val[1] - refw["T_new"])))
+            extra[wl][prec]["error_sample_cells"] = int(len(Tw))
     threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
     return {"value": reps * len(idx) / el, "unit": "cells/s", "cores": int(threads),
             "kind": "oracle",

@@ -91,6 +91,28 @@ def _ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
 
 
+def _check_field(t, name, rows, n, ld, dtype):
+    """The C ABI takes field arrays as [rows][ld] with the cell index fastest
+    (element (j, i) at j * ld + i).  Tensors of another layout (a transposed
+    or Fortran-ordered copy, a column slice) are rejected here instead of
+    being read with the wrong strides."""
+    import torch
+    if t is None:
+        return
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dtype:
+        raise ValueError(f"{name}: expected a CUDA {dtype} tensor")
+    if rows == 1 and t.dim() == 1:
+        if t.shape[0] != n or (n > 1 and t.stride(0) != 1):
+            raise ValueError(f"{name}: expected a contiguous [{n}] tensor")
+        return
+    if t.dim() != 2 or tuple(t.shape) != (rows, n):
+        raise ValueError(f"{name}: expected shape ({rows}, {n}), got {tuple(t.shape)}")
+    if n > 1 and t.stride(1) != 1:
+        raise ValueError(f"{name}: the cell index must be the fastest (stride 1), got strides {t.stride()}")
+    if rows > 1 and t.stride(0) != ld:
+        raise ValueError(f"{name}: leading dimension {t.stride(0)}, expected {ld} (that of the state)")
+
+
 def _stream():
     import torch
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
@@ -178,6 +200,10 @@ class ChemDNN:
             Y_out = torch.empty_like(Y)
         if T_out is None and self.thermo:
             T_out = torch.empty_like(T)
+        f64 = torch.float64
+        for t, nm, r in ((T, "T", 1), (P, "P", 1), (Y, "Y", self.S), (Y_out, "Y_out", self.S),
+                         (T_out, "T_out", 1)):
+            _check_field(t, nm, r, n, ld, f64)
         _check(lib().chem_dnn_step(self._h, n, ld, _ptr(T), _ptr(P), _ptr(Y), _ptr(Y_out),
                                    _ptr(T_out), _ptr(n_bad), _stream()), "chem_dnn_step")
         return Y_out, T_out
@@ -188,6 +214,8 @@ class ChemDNN:
         amax = torch.empty(self.L, dtype=torch.float32, device=T.device)
         n = int(T.shape[0])
         ld = int(Y.stride(0))
+        for t, nm, r in ((T, "T", 1), (P, "P", 1), (Y, "Y", self.S)):
+            _check_field(t, nm, r, n, ld, torch.float64)
         _check(lib().chem_dnn_calibrate(self._h, n, ld, _ptr(T), _ptr(P), _ptr(Y), _ptr(amax),
                                         _stream()), "chem_dnn_calibrate")
         return amax
@@ -206,6 +234,7 @@ class ChemDNN:
         import torch
         B = int(x.shape[1])
         ld = int(x.stride(0))
+        _check_field(x, "x", self.widths[0], B, ld, torch.float32)
         out = torch.empty((self.S, B), dtype=torch.float32, device=x.device)
         if out.stride(0) != ld:
             out = torch.empty((self.S, ld), dtype=torch.float32, device=x.device)[:, :B]
@@ -217,6 +246,8 @@ class ChemDNN:
         import torch
         B = int(x.shape[1])
         ld = int(x.stride(0))
+        _check_field(x, "x", self.widths[0], B, ld, torch.float32)
+        _check_field(grad_out, "grad_out", self.S, B, ld, torch.float32)
         gp = torch.empty_like(params)
         gx = torch.empty((x.shape[0], ld), dtype=torch.float32, device=x.device)[:, :B] \
             if want_grad_x else None
@@ -230,6 +261,12 @@ class ChemDNN:
         import torch
         B = int(T.shape[0])
         ld = int(Y.stride(0))
+        for t, nm, r in ((T, "T", 1), (P, "P", 1), (Y, "Y", self.S)):
+            _check_field(t, nm, r, B, ld, torch.float64)
+        _check_field(target, "target", self.S, B, ld, torch.float32)
+        for t, nm in ((params, "params"), (grads, "grads"), (adam_m, "adam_m"), (adam_v, "adam_v")):
+            if t.dtype != torch.float32 or not t.is_contiguous() or t.numel() != params.numel():
+                raise ValueError(f"{nm}: expected a contiguous float32 tensor like params")
         if loss is None:
             loss = torch.empty(1, dtype=torch.float32, device=T.device)
         _check(lib().chem_dnn_train_step(self._h, B, ld, _ptr(T), _ptr(P), _ptr(Y), _ptr(target),

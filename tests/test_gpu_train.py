@@ -145,3 +145,66 @@ def test_calibration_amax_matches_oracle():
         am = h.calibrate(T, P, Y).cpu().numpy().astype(np.float64)
         ref = chem.layer_input_amax(st.T, st.P, st.Y, net)
         np.testing.assert_allclose(am, ref, rtol=2e-5)
+
+
+def test_training_on_integrator_samples():
+    """Training the 19-400-200-100-17 net on labels from the FP64 stiff
+    integrator (synthetic 17-species, 40-reaction mechanism, dt = 1e-6 s):
+    the first Adam steps match the FP64 oracle's, and the loss falls."""
+    from oracle import kinetics
+    print("case train on integrator labels", flush=True)
+    B = 2048
+    mech = synth.make_mechanism(4)
+    st = synth.make_state(4, B)
+    ts = kinetics.training_set(mech, st, 1e-6, synth.BOXCOX_LAMBDA)
+    ok = ts["ok"]
+    assert ok.mean() > 0.99
+    idx = np.nonzero(ok)[0]
+    sub = synth.State(st.T[idx], st.P[idx], np.ascontiguousarray(st.Y[:, idx]))
+    # (column selection gives a Fortran-ordered array; the ABI wants rows)
+    tgt = np.ascontiguousarray(ts["t"][:, idx])
+    # the net normalises its input with the training set's statistics
+    net = synth.make_net(4)
+    net.in_mean, net.in_std = ts["in_mean"], ts["in_std"]
+    h = make_handle(net, "fp32", max_batch=B)
+    T, P, Y = dev_state(sub)
+    td = torch.tensor(tgt, dtype=torch.float32, device="cuda")
+    p = torch.tensor(net.flat_params(), device="cuda")
+    m, v, g = torch.zeros_like(p), torch.zeros_like(p), torch.empty_like(p)
+    x = ts["x"][:, idx]
+    q = net.flat_params().astype(np.float64)
+    mm, vv = np.zeros_like(q), np.zeros_like(q)
+    losses = []
+    for k in range(1, 41):
+        loss = float(h.train_step(T, P, Y, td, p, g, m, v, k, lr=1e-3).item())
+        losses.append(loss)
+        if k <= 3:
+            r = train.train_step(x, tgt.astype(np.float32).astype(np.float64), q, mm, vv, k, WIDTHS)
+            q, mm, vv = r["params"], r["m"], r["v"]
+            assert abs(r["loss"] - loss) <= 1e-5 * r["loss"], (k, r["loss"], loss)
+    print(f"  loss {losses[0]:.4f} -> {losses[-1]:.4f} after 40 Adam steps", flush=True)
+    assert losses[-1] < 0.7 * losses[0]
+
+
+def test_binding_rejects_wrong_layouts():
+    """Field arrays reach the C ABI as [rows][ld] with the cell index fastest;
+    the binding refuses a transposed or Fortran-ordered tensor instead of
+    passing it with the wrong strides."""
+    print("case binding layouts", flush=True)
+    net = synth.make_net(4)
+    st = synth.make_state(4, 256)
+    h = make_handle(net, "fp32", max_batch=256)
+    T, P, Y = dev_state(st)
+    p = torch.tensor(net.flat_params(), device="cuda")
+    m, v, g = torch.zeros_like(p), torch.zeros_like(p), torch.empty_like(p)
+    tgt_f = torch.tensor(np.asfortranarray(np.zeros((17, 256))), dtype=torch.float32, device="cuda")
+    assert tgt_f.stride() == (1, 17)
+    with pytest.raises(ValueError):
+        h.train_step(T, P, Y, tgt_f, p, g, m, v, 1)
+    with pytest.raises(ValueError):
+        h.step(T, P, Y.t().contiguous().t())
+    with pytest.raises(ValueError):
+        h.step(T.float(), P, Y)
+    # the same data in row layout is accepted
+    h.train_step(T, P, Y, tgt_f.contiguous(), p, g, m, v, 1)
+    torch.cuda.synchronize()
