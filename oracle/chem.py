@@ -50,6 +50,44 @@ def gelu(x):
     return 0.5 * x * (1.0 + np.tanh(SQRT_2_OVER_PI * (x + GELU_CUBIC * x ** 3)))
 
 
+# Tabulated GELU of Sec. 3.3.2: zero below -3, the identity above 3, and a
+# second-order table with interval 0.01 on [-3, 3].  The paper gives no more
+# detail; reading: 600 intervals, each with the second-order Taylor expansion
+# of the tanh-form GELU about the interval's midpoint.
+GELU_TAB_LO, GELU_TAB_HI, GELU_TAB_H = -3.0, 3.0, 0.01
+GELU_TAB_N = 600
+
+
+def gelu_second(x):
+    """d2/dx2 of the tanh-form GELU."""
+    x = np.asarray(x, dtype=np.float64)
+    v = SQRT_2_OVER_PI * (x + GELU_CUBIC * x ** 3)
+    t = np.tanh(v)
+    s2 = 1.0 - t * t                                   # sech^2 v
+    dv = SQRT_2_OVER_PI * (1.0 + 3.0 * GELU_CUBIC * x * x)
+    d2v = SQRT_2_OVER_PI * 6.0 * GELU_CUBIC * x
+    # GELU = x (1 + t)/2:  G'' = t' + x t''/2,  t' = s2 v',  t'' = s2 (v'' - 2 t v'^2)
+    return s2 * dv + 0.5 * x * s2 * (d2v - 2.0 * t * dv * dv)
+
+
+def gelu_table_coeffs():
+    """[600][3] FP64: value, first derivative and half the second derivative
+    of the GELU at the midpoints -3 + (i + 1/2) 0.01."""
+    m = GELU_TAB_LO + (np.arange(GELU_TAB_N) + 0.5) * GELU_TAB_H
+    return np.stack([gelu(m), gelu_grad(m), 0.5 * gelu_second(m)], axis=1)
+
+
+def gelu_table(x, coeffs=None):
+    """The tabulated GELU: c0 + c1 d + c2 d^2 with d the offset from the
+    midpoint of x's interval; 0 below -3, x above 3."""
+    x = np.asarray(x, dtype=np.float64)
+    c = gelu_table_coeffs() if coeffs is None else coeffs
+    i = np.clip(np.floor((x - GELU_TAB_LO) / GELU_TAB_H), 0, GELU_TAB_N - 1).astype(np.int64)
+    d = x - (GELU_TAB_LO + (i + 0.5) * GELU_TAB_H)
+    y = c[i, 0] + d * (c[i, 1] + d * c[i, 2])
+    return np.where(x < GELU_TAB_LO, 0.0, np.where(x > GELU_TAB_HI, x, y))
+
+
 def gelu_grad(x):
     """d/dx of the tanh-form GELU."""
     x = np.asarray(x, dtype=np.float64)
@@ -111,7 +149,7 @@ def features(T, P, Y, in_mean, in_std, lam):
     return (x - np.asarray(in_mean)[:, None]) / np.asarray(in_std)[:, None]
 
 
-def mlp(z, W, b, fmt=None, act_scale=None, w_scale=None, amax=None):
+def mlp(z, W, b, fmt=None, act_scale=None, w_scale=None, amax=None, act=gelu):
     """Fully connected net: hidden layers a_l = GELU(W_l a_(l-1) + b_l), linear
     output layer.  W[l] is [out][in], z is [in][cells].
 
@@ -119,7 +157,8 @@ def mlp(z, W, b, fmt=None, act_scale=None, w_scale=None, amax=None):
     the narrow-format values round(a / s_A) and round(W / s_W) (the paper runs
     weights and activations in FP16, Sec. 3.3.1); their products are summed in
     FP64 and scaled back by s_A s_W before the bias is added.  Scales default
-    to 1.  ``amax`` (a list) receives each layer's input max |a|.
+    to 1.  ``amax`` (a list) receives each layer's input max |a|.  ``act`` is
+    the activation (the tanh-form GELU, or gelu_table).
     """
     a = np.asarray(z, dtype=np.float64)
     L = len(W)
@@ -134,7 +173,7 @@ def mlp(z, W, b, fmt=None, act_scale=None, w_scale=None, amax=None):
             sa = 1.0 if act_scale is None else float(act_scale[l])
             sw = 1.0 if w_scale is None else float(w_scale[l])
             zl = (round_to(Wl / sw, fmt) @ round_to(a / sa, fmt)) * (sa * sw) + bl[:, None]
-        a = gelu(zl) if l < L - 1 else zl
+        a = act(zl) if l < L - 1 else zl
     return a
 
 
@@ -177,7 +216,7 @@ def post(o, T, Y, out_mean, out_std, lam, thermo=None):
     return ynew, T_new, bad
 
 
-def step(T, P, Y, net, fmt=None, act_scale=None, w_scale=None, thermo=None):
+def step(T, P, Y, net, fmt=None, act_scale=None, w_scale=None, thermo=None, act=gelu):
     """One chemistry update of every cell.  ``net`` has the attributes of
     ``synth.Net`` (widths, W, b, in/out statistics, lam).
 
@@ -194,7 +233,7 @@ def step(T, P, Y, net, fmt=None, act_scale=None, w_scale=None, thermo=None):
     z = features(Ts, Ps, Ys, net.in_mean, net.in_std, net.lam)
     W64 = [np.asarray(w, dtype=np.float64) for w in net.W]
     b64 = [np.asarray(v, dtype=np.float64) for v in net.b]
-    o = mlp(z, W64, b64, fmt, act_scale, w_scale)
+    o = mlp(z, W64, b64, fmt, act_scale, w_scale, act=act)
     ynew, tnew, bad = post(o, Ts, Ys, net.out_mean, net.out_std, net.lam, thermo)
     bad = bad | ~fin_in
     ynew = np.where(bad[None, :], Y, ynew)

@@ -267,3 +267,35 @@ def test_step_with_zero_output_layer_returns_input():
     st = _state(n=64)
     r = chem.step(st.T, st.P, st.Y, net)
     np.testing.assert_allclose(r["Y_new"], st.Y / st.Y.sum(axis=0), rtol=1e-13, atol=1e-300)
+
+
+# ------------------------------------------------------------------ tabulated GELU (Sec. 3.3.2)
+def test_gelu_second_derivative_central_differences():
+    x = np.linspace(-5.0, 5.0, 2001)
+    h = 1e-5
+    fd = (chem.gelu_grad(x + h) - chem.gelu_grad(x - h)) / (2 * h)
+    assert np.max(np.abs(fd - chem.gelu_second(x))) <= 1e-8
+
+
+def test_gelu_table_is_exact_at_midpoints_and_within_taylor_bound():
+    """Second-order Taylor expansion about each midpoint: exact there, and off
+    by at most (h/2)^3/6 max|GELU'''| inside [-3, 3]."""
+    m = -3.0 + (np.arange(600) + 0.5) * 0.01
+    np.testing.assert_array_equal(chem.gelu_table(m), chem.gelu(m))
+    x = np.linspace(-3.0, 3.0, 600001)
+    err = np.max(np.abs(chem.gelu_table(x) - chem.gelu(x)))
+    xs = np.linspace(-3.0, 3.0, 60001)
+    h = 1e-4
+    f3 = np.max(np.abs((chem.gelu_second(xs + h) - chem.gelu_second(xs - h)) / (2 * h)))
+    bound = 0.005 ** 3 / 6.0 * f3
+    assert err <= 1.001 * bound, (err, bound)
+    assert err >= 0.5 * bound          # the bound is attained: the expansion is second order
+
+
+def test_gelu_table_outside_and_jump():
+    """Zero below -3 and the identity above 3 (the paper's statement); the jump
+    at the ends is the GELU's own value there."""
+    x = np.array([-50.0, -3.5, -3.000001, 3.000001, 4.0, 60.0])
+    np.testing.assert_array_equal(chem.gelu_table(x), np.where(x < 0, 0.0, x))
+    jump = abs(chem.gelu_table(-2.9999999) - chem.gelu_table(-3.0000001))
+    assert abs(jump - abs(chem.gelu(-3.0))) <= 1e-6
