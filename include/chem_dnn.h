@@ -57,6 +57,15 @@ enum {
     CHEM_DNN_FP8E4M3 = 3  /* OCP FP8 E4M3 operands, saturating RNE, per-layer power-of-two scales */
 };
 
+enum {
+    CHEM_DNN_GELU_TANH = 0,   /* 0.5x(1 + tanh(sqrt(2/pi)(x + 0.044715x^3))) evaluated in FP32 */
+    CHEM_DNN_GELU_TABLE = 1   /* the tabulated GELU of Sec. 3.3.2: 0 for x < -3, x for x > 3, and
+                                 on [-3, 3] 600 intervals of 0.01, each the second-order Taylor
+                                 expansion about its midpoint (error <= 1.7e-8 inside, a jump of
+                                 |GELU(-+3)| = 3.6e-3 at the ends); inference only - training
+                                 always uses the tanh form */
+};
+
 /* Network and transform description.  All pointers are host pointers; the
  * arrays are copied by chem_dnn_init and need not outlive it. */
 typedef struct {
@@ -64,6 +73,8 @@ typedef struct {
     int32_t n_layers;           /* L linear layers; this build supports L = 4 */
     int32_t widths[9];          /* widths[0] = S + 2, widths[L] = S, hidden widths 1..4096 */
     int32_t precision;          /* CHEM_DNN_FP32 / _BF16 / _FP16 / _FP8E4M3 */
+    int32_t gelu_form;          /* CHEM_DNN_GELU_TANH or CHEM_DNN_GELU_TABLE (hidden layers of
+                                   chem_dnn_step and chem_dnn_calibrate) */
     double boxcox_lambda;       /* lam > 0 (0.1 in the workloads shipped) */
     const double *in_mean;      /* [S+2] Z-score mean of x = [T, P, u_1..u_S] */
     const double *in_std;       /* [S+2] Z-score standard deviation, > 0 */
@@ -162,7 +173,7 @@ int32_t chem_dnn_destroy(chem_dnn *h);
 /* Static description of a status code. */
 const char *chem_dnn_strerror(int32_t status);
 
-/* ABI version of this header: 1. */
+/* ABI version of this header: 2 (2 added gelu_form to chem_dnn_desc). */
 int32_t chem_dnn_abi_version(void);
 
 #ifdef __cplusplus

@@ -30,7 +30,7 @@ _fp = C.POINTER(C.c_float)
 
 class Desc(C.Structure):
     _fields_ = [("n_species", C.c_int32), ("n_layers", C.c_int32), ("widths", C.c_int32 * 9),
-                ("precision", C.c_int32), ("boxcox_lambda", C.c_double),
+                ("precision", C.c_int32), ("gelu_form", C.c_int32), ("boxcox_lambda", C.c_double),
                 ("in_mean", _dp), ("in_std", _dp), ("out_mean", _dp), ("out_std", _dp),
                 ("act_amax", _fp), ("thermo_hf", _dp), ("thermo_cp", _dp), ("t_ref", C.c_double),
                 ("max_batch", C.c_int64)]
@@ -125,8 +125,11 @@ def _arr(a, ctype):
     return a, a.ctypes.data_as(C.POINTER(ctype))
 
 
+GELU_FORMS = {"tanh": 0, "table": 1}
+
+
 def make_desc(widths, precision, in_mean, in_std, out_mean=None, out_std=None, act_amax=None,
-              thermo=None, max_batch=0, lam=0.1):
+              thermo=None, max_batch=0, lam=0.1, gelu="tanh"):
     """Fills a Desc; returns (desc, keepalive) - keep the second alive while the
     desc is in use."""
     d = Desc()
@@ -136,6 +139,7 @@ def make_desc(widths, precision, in_mean, in_std, out_mean=None, out_std=None, a
     for i, w in enumerate(widths):
         d.widths[i] = w
     d.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    d.gelu_form = GELU_FORMS[gelu] if isinstance(gelu, str) else int(gelu)
     d.boxcox_lambda = float(lam)
     keep = []
     for name, val, ct in (("in_mean", in_mean, C.c_double), ("in_std", in_std, C.c_double),
@@ -168,7 +172,7 @@ class ChemDNN:
     """
 
     def __init__(self, widths, precision, params, in_mean, in_std, out_mean=None, out_std=None,
-                 act_amax=None, thermo=None, max_batch=0, lam=0.1):
+                 act_amax=None, thermo=None, max_batch=0, lam=0.1, gelu="tanh"):
         import torch
         self.widths = tuple(int(w) for w in widths)
         self.S = self.widths[-1]
@@ -176,7 +180,7 @@ class ChemDNN:
         self.precision = precision
         self.thermo = thermo is not None
         desc, keep = make_desc(self.widths, precision, in_mean, in_std, out_mean, out_std,
-                               act_amax, thermo, max_batch, lam)
+                               act_amax, thermo, max_batch, lam, gelu)
         nbytes = workspace_bytes(desc)
         dev = params.device
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)

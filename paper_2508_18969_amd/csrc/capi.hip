@@ -29,21 +29,42 @@ struct chem_dnn {
   TrainScratch tr;
   int64_t max_batch;
   int thermo;
+  int gelu_form;
+  float *gtab;
   // host copies kept alive for the asynchronous uploads
   float hfc[FConst::N];
   double hdc[DConst::N];
+  float hgtab[GTAB_N * 4];
 };
 
 namespace {
 
 constexpr size_t kAlign = 256;
+
+// Coefficients of the tabulated GELU: per interval i of [-3, 3] (width
+// 0.01), the value, first derivative and half the second derivative of
+// G(x) = x (1 + tanh v) / 2, v = sqrt(2/pi) (x + 0.044715 x^3), at the
+// midpoint, computed in FP64.  With t = tanh v and s = 1 - t^2:
+// G' = (1 + t)/2 + x s v'/2 and G'' = s v' + x (s v'' - 2 t s v'^2)/2.
+void fill_gelu_table(float *tab) {
+  const double c = sqrt(2.0 / M_PI), k = 0.044715;
+  for (int i = 0; i < GTAB_N; ++i) {
+    const double x = -3.0 + (i + 0.5) * 0.01;
+    const double v = c * (x + k * x * x * x), t = tanh(v), s = 1.0 - t * t;
+    const double v1 = c * (1.0 + 3.0 * k * x * x), v2 = c * 6.0 * k * x;
+    tab[4 * i + 0] = (float)(0.5 * x * (1.0 + t));
+    tab[4 * i + 1] = (float)(0.5 * (1.0 + t) + 0.5 * x * s * v1);
+    tab[4 * i + 2] = (float)(0.5 * (s * v1 + 0.5 * x * (s * v2 - 2.0 * t * s * v1 * v1)));
+    tab[4 * i + 3] = 0.0f;
+  }
+}
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 int32_t hip_status(hipError_t e) { return e == hipSuccess ? CHEM_DNN_OK : CHEM_DNN_EHIP; }
 
 // Offsets of every sub-buffer inside the workspace.
 struct WsPlan {
-  size_t fc, dc, amax, bias[4], w[4], train, total;
+  size_t fc, dc, amax, gtab, bias[4], w[4], train, total;
 };
 
 int32_t check_desc(const chem_dnn_desc *d) {
@@ -55,6 +76,7 @@ int32_t check_desc(const chem_dnn_desc *d) {
   for (int l = 1; l < L; ++l)
     if (d->widths[l] < 1 || d->widths[l] > 4096) return CHEM_DNN_EINVAL;
   if (d->precision < CHEM_DNN_FP32 || d->precision > CHEM_DNN_FP8E4M3) return CHEM_DNN_EINVAL;
+  if (d->gelu_form != CHEM_DNN_GELU_TANH && d->gelu_form != CHEM_DNN_GELU_TABLE) return CHEM_DNN_EINVAL;
   if (!(d->boxcox_lambda > 0.0) || !isfinite(d->boxcox_lambda)) return CHEM_DNN_EINVAL;
   if (!d->in_mean || !d->in_std) return CHEM_DNN_EINVAL;
   for (int f = 0; f < S + 2; ++f)
@@ -74,6 +96,7 @@ int32_t plan(const chem_dnn_desc *d, NetLayout *lay, WsPlan *p) {
     return CHEM_DNN_EUNSUPPORTED;
   size_t off = 0;
   p->fc = off; off = align_up(off + FConst::N * sizeof(float));
+  p->gtab = off; off = align_up(off + GTAB_N * 4 * sizeof(float));
   p->dc = off; off = align_up(off + DConst::N * sizeof(double));
   p->amax = off; off = align_up(off + 8 * sizeof(uint32_t));
   for (int l = 0; l < 4; ++l) {
@@ -149,6 +172,7 @@ StepArgs step_args(chem_dnn *h, int64_t n, int64_t ld, const double *T, const do
   for (int l = 0; l < 4; ++l) { a.w[l] = h->wpack[l]; a.b[l] = h->bias[l]; }
   a.fc = h->fc; a.dc = h->dc;
   a.amax = nullptr;
+  a.gtab = h->gtab;
   a.S = h->S;
   a.thermo = h->thermo;
   return a;
@@ -163,7 +187,7 @@ int grid_for(const chem_dnn *h, int64_t ntiles) {
 
 extern "C" {
 
-int32_t chem_dnn_abi_version(void) { return 1; }
+int32_t chem_dnn_abi_version(void) { return 2; }
 
 const char *chem_dnn_strerror(int32_t st) {
   switch (st) {
@@ -218,6 +242,7 @@ int32_t chem_dnn_init(const chem_dnn_desc *d, const float *params, void *workspa
   h->ws = (uint8_t *)workspace;
   h->ws_bytes = workspace_bytes;
   h->fc = (float *)(h->ws + p.fc);
+  h->gtab = (float *)(h->ws + p.gtab);
   h->dc = (double *)(h->ws + p.dc);
   h->amax_bits = (uint32_t *)(h->ws + p.amax);
   for (int l = 0; l < 4; ++l) {
@@ -227,6 +252,8 @@ int32_t chem_dnn_init(const chem_dnn_desc *d, const float *params, void *workspa
   h->max_batch = d->max_batch;
   train_scratch_layout(&h->tr, h->ws + p.train, d->widths, d->max_batch);
   h->thermo = d->thermo_hf ? 1 : 0;
+  h->gelu_form = d->gelu_form;
+  fill_gelu_table(h->hgtab);
 
   // constants
   const double lam = d->boxcox_lambda;
@@ -265,6 +292,7 @@ int32_t chem_dnn_init(const chem_dnn_desc *d, const float *params, void *workspa
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = hipMemcpyAsync(h->fc, h->hfc, sizeof(h->hfc), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(h->dc, h->hdc, sizeof(h->hdc), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(h->gtab, h->hgtab, sizeof(h->hgtab), hipMemcpyHostToDevice, s);
   if (e != hipSuccess) {
     delete h;
     return CHEM_DNN_EHIP;
@@ -296,7 +324,8 @@ int32_t chem_dnn_step(chem_dnn *h, int64_t n, int64_t ld, const double *T, const
   if (!T || !P || !Y || !Y_out) return CHEM_DNN_EINVAL;
   if (T_out && !h->thermo) return CHEM_DNN_EINVAL;
   StepArgs a = step_args(h, n, ld, T, P, Y, Y_out, T_out, n_bad);
-  return hip_status(h->lay.step(a, grid_for(h, a.ntiles), (hipStream_t)stream));
+  auto launch = h->gelu_form == CHEM_DNN_GELU_TABLE ? h->lay.step_tab : h->lay.step;
+  return hip_status(launch(a, grid_for(h, a.ntiles), (hipStream_t)stream));
 }
 
 int32_t chem_dnn_calibrate(chem_dnn *h, int64_t n, int64_t ld, const double *T, const double *P,
@@ -309,7 +338,8 @@ int32_t chem_dnn_calibrate(chem_dnn *h, int64_t n, int64_t ld, const double *T, 
   if (!T || !P || !Y) return CHEM_DNN_EINVAL;
   StepArgs a = step_args(h, n, ld, T, P, Y, nullptr, nullptr, nullptr);
   a.amax = amax;
-  return hip_status(h->lay.calib(a, grid_for(h, a.ntiles), s));
+  auto launch = h->gelu_form == CHEM_DNN_GELU_TABLE ? h->lay.calib_tab : h->lay.calib;
+  return hip_status(launch(a, grid_for(h, a.ntiles), s));
 }
 
 int32_t chem_dnn_get_scales(chem_dnn *h, float *act_scale, float *w_scale, void *stream) {

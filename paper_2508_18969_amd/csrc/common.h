@@ -49,6 +49,19 @@ __device__ __forceinline__ float gelu(float x) {
   return x * __builtin_amdgcn_rcpf(1.0f + e);
 }
 
+// Tabulated GELU (Sec. 3.3.2): 0 below -3, x above 3; in between, the
+// interval i = floor((x + 3) / 0.01) holds the second-order expansion
+// c0 + c1 d + c2 d^2 about its midpoint (d = x - midpoint).  `tab` is the
+// LDS copy of the table, (c0, c1, c2, 0) per interval.
+__device__ __forceinline__ float gelu_tab(float x, const f4 *tab) {
+  int i = (int)((x + 3.0f) * 100.0f);
+  i = i < 0 ? 0 : (i > 599 ? 599 : i);
+  const float d = x - __builtin_fmaf((float)i, 0.01f, -2.995f);
+  const f4 c = tab[i];
+  const float y = __builtin_fmaf(__builtin_fmaf(c[2], d, c[1]), d, c[0]);
+  return x < -3.0f ? 0.0f : (x > 3.0f ? x : y);
+}
+
 // Y^lam in FP32 from an FP64 mass fraction, via the exponent split
 // y = m 2^e (m in [1, 2)) so that values far below FLT_MIN keep their
 // magnitude.  Non-positive, NaN or subnormal-double inputs give 0

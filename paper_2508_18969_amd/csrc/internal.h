@@ -45,8 +45,13 @@ struct StepArgs {
   const float *fc;       // FConst block
   const double *dc;      // DConst block
   float *amax;           // calibration output [4] (bit pattern max)
+  const float *gtab;     // tabulated GELU: [GTAB_N][4] (c0, c1, c2, 0) per interval
   int S, thermo;
 };
+
+// Tabulated GELU: GTAB_N intervals of width 1/GTAB_INV_H from GTAB_LO.
+constexpr int GTAB_N = 600;
+constexpr float GTAB_LO = -3.0f, GTAB_HI = 3.0f, GTAB_INV_H = 100.0f, GTAB_H = 0.01f;
 
 // Shape and layout of one compiled network configuration.
 struct NetLayout {
@@ -56,7 +61,9 @@ struct NetLayout {
   int lds_bytes;
   // launches
   hipError_t (*step)(const StepArgs &, int grid, hipStream_t);
+  hipError_t (*step_tab)(const StepArgs &, int grid, hipStream_t);   // tabulated GELU
   hipError_t (*calib)(const StepArgs &, int grid, hipStream_t);  // FP32 only, else null
+  hipError_t (*calib_tab)(const StepArgs &, int grid, hipStream_t);
   hipError_t (*prepare)();     // one-time function attributes
 };
 

@@ -21,29 +21,32 @@
 
 namespace chemdnn {
 
-// Split of R output row-blocks x CB cell-blocks over four waves: each wave
+// Split of R output row-blocks x CB cell-blocks over NW waves: each wave
 // owns F whole row-blocks (all cell-blocks) plus NREM leftover tiles.
-template <int R, int CB> struct Split {
-  static constexpr int F = R / 4;
-  static constexpr int RR = R % 4;
-  static constexpr int NREM = RR * CB / 4;
+template <int R, int CB, int NW> struct Split {
+  static constexpr int F = R / NW;
+  static constexpr int RR = R % NW;
+  static constexpr int NREM = RR * CB / NW;
   static constexpr int T = F * CB + NREM;
-  static_assert((RR * CB) % 4 == 0, "row-blocks must split evenly over four waves");
-  static __device__ __forceinline__ int rem_rb(int w, int k) { return 4 * F + (w * NREM + k) / CB; }
+  static_assert((RR * CB) % NW == 0, "row-blocks must split evenly over the waves");
+  static __device__ __forceinline__ int rem_rb(int w, int k) { return NW * F + (w * NREM + k) / CB; }
   static __device__ __forceinline__ int rem_cb(int w, int k) { return (w * NREM + k) % CB; }
 };
 
 // Output rows a layer computes: h rounded up to row-blocks of 16 such that
-// the row-blocks split evenly over the four waves (see Split); with `whole`,
-// to a multiple of four row-blocks, so that no wave has leftover tiles.
-constexpr int padN(int h, int cb, bool whole) {
-  int p = roundup(h, whole ? 64 : 16);
-  while ((((p / 16) % 4) * cb) % 4) p += 16;
+// the row-blocks split evenly over the nw waves (see Split); with `whole`,
+// to a multiple of nw row-blocks, so that no wave has leftover tiles.
+constexpr int padN(int h, int cb, bool whole, int nw) {
+  int p = roundup(h, whole ? 16 * nw : 16);
+  while ((((p / 16) % nw) * cb) % nw) p += 16;
   return p;
 }
 
-template <class Op_, int CB_, int H1_, int H2_, int H3_> struct Cfg {
+template <class Op_, int CB_, int NW_, int H1_, int H2_, int H3_> struct Cfg {
   using Op = Op_;
+  // NW waves per workgroup (4: one per SIMD; 8: two per SIMD, which hides
+  // one wave's memory waits behind the other's work, at half the registers)
+  static constexpr int NW = NW_;
   using frag_t = typename Op::frag_t;
   static constexpr int KS = Op::KS, FRAG = Op::FRAG, EB = Op::EB, CB = CB_, MC = 16 * CB_;
   static constexpr int NQ1 = (32 + KS - 1) / KS;    // layer-1 k-steps (inputs <= 32)
@@ -52,13 +55,13 @@ template <class Op_, int CB_, int H1_, int H2_, int H3_> struct Cfg {
   // layers 2 and 3 compute H2N / H3N rows; as the next layer's input they
   // are zero-padded to whole k-steps (H2P / H3P)
   // FP8 fragments take twice the registers: no leftover tiles there
-  static constexpr int H2N = padN(H2_, CB_, FRAG == 32), H3N = padN(H3_, CB_, FRAG == 32);
+  static constexpr int H2N = padN(H2_, CB_, FRAG == 32, NW_), H3N = padN(H3_, CB_, FRAG == 32, NW_);
   static constexpr int H2P = roundup(H2N, KS), H3P = roundup(H3N, KS);
   static constexpr int R1 = H1P / 16, R2 = H2N / 16, R3 = H3N / 16, R4 = 2;
   static constexpr int NQ2 = H1P / KS, NQ3 = H2P / KS, NQ4 = H3P / KS;
   static constexpr int NSC = H1P / SC, RB1W = SC / 64, QSC = SC / KS, RPQ = KS / 16;
-  using S2 = Split<R2, CB_>;
-  using S3 = Split<R3, CB_>;
+  using S2 = Split<R2, CB_, NW_>;
+  using S3 = Split<R3, CB_, NW_>;
   static constexpr int QBYTES = CB * 64 * FRAG;     // one k-step of a tile's activations
   static constexpr int NW1 = RB1W * NQ1;             // layer-1 fragments per wave per chunk
   static constexpr int NBIAS = H1P + H2N + H3N + 32; // biases of all layers, FP32
@@ -71,12 +74,16 @@ template <class Op_, int CB_, int H1_, int H2_, int H3_> struct Cfg {
   static constexpr int NW2 = S2::F + S2::NREM;               // layer-2 fragments per wave per k-step
   static constexpr int NB2 = QSC % 2 == 0 ? 2 : 1;           // layer-2 register buffers
   static constexpr int A2_BYTES = Max<NQ3, NQ4>::v * QBYTES;
-  // output-layer weights are copied to LDS once per workgroup when they fit
+  // The LDS tail holds the GELU table (tabulated form only), then the
+  // output-layer weights, copied once per workgroup when they fit.
   static constexpr int W4_BYTES = R4 * NQ4 * 64 * FRAG;
-  static constexpr int LDS_W4 = LDS_A2 + A2_BYTES;
-  static constexpr bool W4_LDS = LDS_W4 + W4_BYTES <= 160 * 1024;
-  static constexpr int LDS_BYTES = LDS_W4 + (W4_LDS ? W4_BYTES : 0);
-  static_assert(LDS_BYTES <= 160 * 1024, "LDS budget");
+  static constexpr int TAB_BYTES = GTAB_N * 16;
+  static constexpr int LDS_TAIL = LDS_A2 + A2_BYTES;
+  static constexpr int lds_w4(bool gt) { return LDS_TAIL + (gt ? TAB_BYTES : 0); }
+  static constexpr bool w4_lds(bool gt) { return lds_w4(gt) + W4_BYTES <= 160 * 1024; }
+  static constexpr int lds_bytes(bool gt) { return lds_w4(gt) + (w4_lds(gt) ? W4_BYTES : 0); }
+  static constexpr int LDS_BYTES = lds_bytes(false);
+  static_assert(lds_bytes(true) <= 160 * 1024, "LDS budget");
 };
 
 // Pointer into global memory: loads through it are global (not flat) loads.
@@ -110,8 +117,8 @@ __device__ __forceinline__ frag_t lds_frag(const uint8_t *base, int idx, int lan
 
 __device__ __forceinline__ float umaxf(float a, float b) { return a > b ? a : b; }
 
-template <class C, bool CALIB>
-__global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
+template <class C, bool CALIB, bool GT>
+__global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
   using Op = typename C::Op;
   using frag_t = typename C::frag_t;
   using S2 = typename C::S2;
@@ -153,9 +160,19 @@ __global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
   float *const fcl = (float *)(smem + C::LDS_FC);
   for (int i = threadIdx.x; i < DConst::N; i += blockDim.x) dcl[i] = a.dc[i];
   for (int i = threadIdx.x; i < FConst::N; i += blockDim.x) fcl[i] = a.fc[i];
-  if constexpr (C::W4_LDS)
+  constexpr bool W4L = C::w4_lds(GT);
+  constexpr int LW4 = C::lds_w4(GT);
+  if constexpr (W4L)
     for (int i = threadIdx.x; i < C::W4_BYTES / 16; i += blockDim.x)
-      ((i4 *)(smem + C::LDS_W4))[i] = ((const i4 *)W4g)[i];
+      ((i4 *)(smem + LW4))[i] = ((const i4 *)W4g)[i];
+  const f4 *const tabl = (const f4 *)(smem + C::LDS_TAIL);
+  if constexpr (GT)
+    for (int i = threadIdx.x; i < GTAB_N; i += blockDim.x) ((f4 *)(smem + C::LDS_TAIL))[i] = ((const f4 *)a.gtab)[i];
+  // hidden-layer activation: the tanh form, or the table
+  auto act = [&](float x) {
+    if constexpr (GT) return gelu_tab(x, tabl);
+    else return gelu(x);
+  };
   __syncthreads();
 
   // The preprocess state is loaded one tile ahead: lane (cell 16w + cl,
@@ -172,7 +189,7 @@ __global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
       xin[j] = __builtin_nontemporal_load(f == 0 ? &a.T[ii] : f == 1 ? &a.P[ii] : &a.Y[(int64_t)(s > 0 ? s : 0) * a.ld + ii]);
     }
   };
-  if (CB == 4 || w < CB) load_xin(blockIdx.x);
+  if (C::NW == CB || w < CB) load_xin(blockIdx.x);
 
   for (int64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
     const int64_t cell0 = tile * C::MC;
@@ -184,7 +201,7 @@ __global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
 
     // ------------------------------------------------------------ preprocess
     // Lane (cell 16w + cl, group g) computes input features f = 16h + 4g + r.
-    if (CB == 4 || w < CB) {
+    if (C::NW == CB || w < CB) {
       const int64_t i = cell0 + 16 * w + cl;
       const bool valid = i < a.n;
       f4 v[2];
@@ -227,9 +244,13 @@ __global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
     // `buf`).  Value v of the chunk is output value v % 4 of tile v / 4:
     // row-block v / (4 CB) of this wave, cell-block (v / 4) % CB.
     constexpr int NV1 = C::RB1W * CB * 4;              // activation values per lane per chunk
+    // layer 1 is computed by the first L1W waves (one chunk has SC / 16 row-blocks)
+    constexpr int L1W = C::SC / 16 / C::RB1W;
+    const bool l1wave = C::NW == L1W || w < L1W;
     f4 acc1[C::RB1W][CB];
     f4 y1[C::RB1W][CB];
     auto layer1_mma = [&](int sc, const frag_t (&w1f)[C::NW1]) {
+      if (!l1wave) return;
       // the input fragments, re-read per chunk (cheaper than keeping them
       // live through the layer-2 loop)
       frag_t a0[C::NQ1][CB];
@@ -250,6 +271,7 @@ __global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
     };
     // activation values [v0, v1) of chunk sc; a tile is stored with its last value
     auto layer1_act = [&](int sc, int buf, int v0, int v1) {
+      if (!l1wave) return;
       uint8_t *dst = A1 + buf * C::QSC * C::QBYTES;
 #pragma unroll
       for (int v = 0; v < NV1; ++v) {
@@ -259,7 +281,7 @@ __global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
         const int rb = sc * (C::SC / 16) + rbl;
         const float bias = B1[16 * rb + 4 * g + r];
         const float zz = Op::SCALED ? __builtin_fmaf(acc1[ii][cb][r], sout[0], bias) : acc1[ii][cb][r];
-        y1[ii][cb][r] = gelu(zz);
+        y1[ii][cb][r] = act(zz);
         if (r == 3) {
           f4 y = y1[ii][cb];
           if (CALIB && cell0 + 16 * cb + cl < a.n)
@@ -301,6 +323,7 @@ __global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
     };
     frag_t w1r[C::NW1];
     auto w1_load = [&](int c) {
+      if (!l1wave) return;
       const int cs = c < C::NSC ? c : c - C::NSC;
 #pragma unroll
       for (int ii = 0; ii < C::RB1W; ++ii)
@@ -387,7 +410,7 @@ __global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
     // rows past the computed ones, up to the next k-step boundary, are zero
     auto zero_pad = [&](int r0, int r1) {
 #pragma unroll
-      for (int t = w; t < (r1 - r0) * CB; t += 4) put(A2, r0 + t / CB, t % CB, f4{0.f, 0.f, 0.f, 0.f});
+      for (int t = w; t < (r1 - r0) * CB; t += C::NW) put(A2, r0 + t / CB, t % CB, f4{0.f, 0.f, 0.f, 0.f});
     };
     {
 #pragma unroll
@@ -398,7 +421,7 @@ __global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
         f4 y;
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-          y[r] = gelu(Op::SCALED ? __builtin_fmaf(acc2[t][r], sout[1], bias[r]) : acc2[t][r]);
+          y[r] = act(Op::SCALED ? __builtin_fmaf(acc2[t][r], sout[1], bias[r]) : acc2[t][r]);
         if (CALIB && cell0 + 16 * cb + cl < a.n)
 #pragma unroll
           for (int r = 0; r < 4; ++r) amx[2] = umaxf(amx[2], __builtin_fabsf(y[r]));
@@ -494,8 +517,8 @@ __global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
     const int64_t ipost = cell0 + 16 * w + cl;
     const bool vpost = ipost < a.n;
     const int64_t icp = vpost ? ipost : 0;
-    if (CB == 4 || w < CB) load_xin(tile + gridDim.x);
-    if (!CALIB && (CB == 4 || w < CB)) {
+    if (C::NW == CB || w < CB) load_xin(tile + gridDim.x);
+    if (!CALIB && (C::NW == CB || w < CB)) {
       // unconditional loads from clamped, valid addresses: no branches
       Tc = __builtin_nontemporal_load(&a.T[icp]);
       Pc = __builtin_nontemporal_load(&a.P[icp]);
@@ -517,7 +540,7 @@ __global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
         f4 y;
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-          y[r] = gelu(Op::SCALED ? __builtin_fmaf(acc3[t][r], sout[2], bias[r]) : acc3[t][r]);
+          y[r] = act(Op::SCALED ? __builtin_fmaf(acc3[t][r], sout[2], bias[r]) : acc3[t][r]);
         if (CALIB && cell0 + 16 * cb + cl < a.n)
 #pragma unroll
           for (int r = 0; r < 4; ++r) amx[3] = umaxf(amx[3], __builtin_fabsf(y[r]));
@@ -546,8 +569,8 @@ __global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
         for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
           for (int q = 0; q < NQ4L; ++q)
-            w4r[rb][q] = C::W4_LDS ? lds_frag<frag_t>(smem + C::LDS_W4, rb * C::NQ4 + q0 + q, lane)
-                                   : ldg_frag<frag_t>(W4, rb * C::NQ4 + q0 + q, lane);
+            w4r[rb][q] = W4L ? lds_frag<frag_t>(smem + LW4, rb * C::NQ4 + q0 + q, lane)
+                             : ldg_frag<frag_t>(W4, rb * C::NQ4 + q0 + q, lane);
 #pragma unroll
         for (int q = 0; q < NQ4L; ++q) {
           const frag_t af = lds_frag<frag_t>(A2, (q0 + q) * CB + w, lane);
@@ -670,23 +693,29 @@ __global__ __launch_bounds__(256, 1) void chem_step_kernel(StepArgs a) {
 }
 
 // ------------------------------------------------------------------ launchers
-template <class C>
+template <class C, bool GT>
 static hipError_t launch_step(const StepArgs &a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((chem_step_kernel<C, false>), dim3(grid), dim3(256), C::LDS_BYTES, s, a);
+  hipLaunchKernelGGL((chem_step_kernel<C, false, GT>), dim3(grid), dim3(C::NW * 64),
+                     C::lds_bytes(GT), s, a);
   return hipGetLastError();
 }
-template <class C>
+template <class C, bool GT>
 static hipError_t launch_calib(const StepArgs &a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((chem_step_kernel<C, true>), dim3(grid), dim3(256), C::LDS_BYTES, s, a);
+  hipLaunchKernelGGL((chem_step_kernel<C, true, GT>), dim3(grid), dim3(C::NW * 64),
+                     C::lds_bytes(GT), s, a);
   return hipGetLastError();
+}
+template <class C, bool CALIB, bool GT>
+static hipError_t set_lds_limit() {
+  return hipFuncSetAttribute((const void *)chem_step_kernel<C, CALIB, GT>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, C::lds_bytes(GT));
 }
 template <class C, bool WITH_CALIB>
 static hipError_t prepare() {
-  hipError_t e = hipFuncSetAttribute((const void *)chem_step_kernel<C, false>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, C::LDS_BYTES);
-  if (e == hipSuccess && WITH_CALIB)
-    e = hipFuncSetAttribute((const void *)chem_step_kernel<C, true>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, C::LDS_BYTES);
+  hipError_t e = set_lds_limit<C, false, false>();
+  if (e == hipSuccess) e = set_lds_limit<C, false, true>();
+  if (e == hipSuccess && WITH_CALIB) e = set_lds_limit<C, true, false>();
+  if (e == hipSuccess && WITH_CALIB) e = set_lds_limit<C, true, true>();
   return e;
 }
 
@@ -699,8 +728,10 @@ static void fill_layout(NetLayout *L) {
   L->R[0] = C::R1; L->R[1] = C::R2; L->R[2] = C::R3; L->R[3] = C::R4;
   L->NQ[0] = C::NQ1; L->NQ[1] = C::NQ2; L->NQ[2] = C::NQ3; L->NQ[3] = C::NQ4;
   L->lds_bytes = C::LDS_BYTES;
-  L->step = launch_step<C>;
-  L->calib = WITH_CALIB ? launch_calib<C> : nullptr;
+  L->step = launch_step<C, false>;
+  L->step_tab = launch_step<C, true>;
+  L->calib = WITH_CALIB ? launch_calib<C, false> : nullptr;
+  L->calib_tab = WITH_CALIB ? launch_calib<C, true> : nullptr;
   L->prepare = prepare<C, WITH_CALIB>;
 }
 
@@ -710,10 +741,10 @@ bool find_layout(int p, int h1, int h2, int h3, NetLayout *out) {
 #define CHEM_SHAPE(H1, H2, H3)                                                        \
   if (h1 == H1 && h2 == H2 && h3 == H3) {                                             \
     switch (p) {                                                                      \
-      case P_FP32: fill_layout<Cfg<OpF32, 2, H1, H2, H3>, true>(out); return true;    \
-      case P_BF16: fill_layout<Cfg<OpBF16, 4, H1, H2, H3>, false>(out); return true;  \
-      case P_FP16: fill_layout<Cfg<OpF16, 4, H1, H2, H3>, false>(out); return true;   \
-      case P_FP8: fill_layout<Cfg<OpF8, 3, H1, H2, H3>, false>(out); return true;     \
+      case P_FP32: fill_layout<Cfg<OpF32, 2, 4, H1, H2, H3>, true>(out); return true;   \
+      case P_BF16: fill_layout<Cfg<OpBF16, 4, 4, H1, H2, H3>, false>(out); return true; \
+      case P_FP16: fill_layout<Cfg<OpF16, 4, 4, H1, H2, H3>, false>(out); return true;  \
+      case P_FP8: fill_layout<Cfg<OpF8, 3, 4, H1, H2, H3>, false>(out); return true;    \
       default: return false;                                                          \
     }                                                                                 \
   }

@@ -27,7 +27,7 @@ def test_header_declares_what_the_library_exports(L):
     lib = L.lib()
     for name in decl:
         assert hasattr(lib, name), name
-    assert lib.chem_dnn_abi_version() == 1
+    assert lib.chem_dnn_abi_version() == 2
     for st in (0, -1, -2, -3, -4, -5):
         assert L.strerror(st) and L.strerror(st) != "unknown status"
 
@@ -50,7 +50,8 @@ def test_workspace_bytes_and_validation(L):
            dict(widths=(19, 0, 200, 100, 17)),
            dict(precision=7),
            dict(in_std=np.zeros(19)),
-           dict(precision="fp8")]                          # FP8 needs act_amax
+           dict(precision="fp8"),                          # FP8 needs act_amax
+           dict(gelu=2)]                                   # no such activation form
     for kw in bad:
         d3, k3 = _desc(L, **kw)
         with pytest.raises(L.ChemDNNError) as e:

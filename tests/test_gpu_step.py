@@ -167,6 +167,51 @@ def test_fp8_matches_emulation(config, n):
     np.testing.assert_allclose(Yg.sum(axis=0), 1.0, atol=1e-13)
 
 
+# ------------------------------------------------------------------ tabulated GELU
+@pytest.mark.parametrize("config,n", [(1, 4096 - 3), (2, 2048 + 5)])
+def test_gelu_table_fp32_matches_oracle(config, n):
+    """FP32 operands with the tabulated GELU (Sec. 3.3.2) against the FP64
+    oracle evaluating the same table: the same 1e-5 bound as the tanh form."""
+    _note(f"case gelu table fp32 config={config} n={n}")
+    net = synth.make_net(config)
+    S = 17 if config == 1 else 29
+    thermo = synth.make_thermo(config, S)
+    st = synth.make_state(config, n)
+    h = make_handle(net, "fp32", thermo=thermo, gelu="table")
+    Yg, Tg, nbad = _run(h, st)
+    ref = chem.step(st.T, st.P, st.Y, net, thermo=thermo, act=chem.gelu_table)
+    assert nbad == 0
+    e_y = rel_err(Yg, ref["Y_new"])
+    e_t = rel_err(Tg, ref["T_new"], floor=1.0)
+    exact = chem.step(st.T, st.P, st.Y, net, thermo=thermo)
+    _note(f"  rel err Y {e_y:.3e}  T {e_t:.3e} | table vs tanh form (oracle): max abs dY "
+          f"{np.abs(ref['Y_new'] - exact['Y_new']).max():.2e}")
+    assert e_y <= 1e-5
+    assert e_t <= 1e-5
+
+
+def test_gelu_table_bf16_matches_emulation():
+    """BF16 operands with the tabulated GELU against the emulation with the
+    same table; the statistical bar of the narrow formats."""
+    _note("case gelu table bf16 n=4096+11")
+    net = synth.make_net(2)
+    thermo = synth.make_thermo(2, 29)
+    st = synth.make_state(2, 4096 + 11)
+    h = make_handle(net, "bf16", thermo=thermo, gelu="table")
+    Yg, Tg, _ = _run(h, st)
+    emu = chem.step(st.T, st.P, st.Y, net, fmt="bf16", thermo=thermo, act=chem.gelu_table)
+    ex = chem.step(st.T, st.P, st.Y, net, thermo=thermo, act=chem.gelu_table)
+    ge, ee = Yg - emu["Y_new"], emu["Y_new"] - ex["Y_new"]
+    rg, re = _rel(Yg, emu["Y_new"]), _rel(emu["Y_new"], ex["Y_new"])
+    rms_g, rms_e = np.sqrt(np.mean(ge ** 2)), np.sqrt(np.mean(ee ** 2))
+    _note(f"  gpu-emu: rms {rms_g:.2e} med {np.median(rg):.2e} max {rg.max():.2e} | "
+          f"emu-fp64: rms {rms_e:.2e} med {np.median(re):.2e} max {re.max():.2e}")
+    assert rms_g <= 0.25 * rms_e
+    assert np.median(rg) <= 0.05 * np.median(re)
+    assert np.quantile(rg, 0.99) <= 0.5 * np.quantile(re, 0.99)
+    assert rg.max() <= 0.5 * re.max()
+
+
 # ------------------------------------------------------------------ properties
 def test_cells_are_independent_and_runs_deterministic():
     _note("case independence bf16")
