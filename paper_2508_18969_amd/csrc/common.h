@@ -67,14 +67,36 @@ __device__ __forceinline__ float gelu_tab(float x, const f4 *tab) {
 // magnitude.  Non-positive, NaN or subnormal-double inputs give 0
 // (y^lam < 1e-30 for subnormal doubles).
 __device__ __forceinline__ float ypow(double y, float lam) {
-  if (!(y > 0.0)) return 0.0f;
-  uint64_t bits = __builtin_bit_cast(uint64_t, y);
-  int ef = (int)((bits >> 52) & 0x7ff);
-  if (ef == 0) return 0.0f;
-  if (ef == 0x7ff) return __builtin_inff();
-  double m = __builtin_bit_cast(double, (bits & 0x000fffffffffffffull) | 0x3ff0000000000000ull);
-  float l2 = __builtin_amdgcn_logf((float)m) + (float)(ef - 1023);
-  return __builtin_amdgcn_exp2f(lam * l2);
+  const uint64_t bits = __builtin_bit_cast(uint64_t, y);
+  const int ef = (int)((bits >> 52) & 0x7ff);
+  const double m = __builtin_bit_cast(double, (bits & 0x000fffffffffffffull) | 0x3ff0000000000000ull);
+  const float l2 = __builtin_amdgcn_logf((float)m) + (float)(ef - 1023);
+  const float r = __builtin_amdgcn_exp2f(lam * l2);
+  // selects, no branches: 0 for y <= 0, NaN or subnormal; inf for +inf
+  return (y > 0.0 && ef != 0) ? (ef == 0x7ff ? __builtin_inff() : r) : 0.0f;
+}
+
+// Sums and reductions over the lane quartet {l, l ^ 16, l ^ 32, l ^ 48} (the
+// four lanes of one cell) with the row-swap permutes: swapping odd rows of
+// one copy with even rows of another leaves, per lane, its own row's value
+// in one result and the partner row's in the other.
+__device__ __forceinline__ double quad_sum(double v) {
+  uint64_t u = __builtin_bit_cast(uint64_t, v);
+  auto l = __builtin_amdgcn_permlane16_swap((uint32_t)u, (uint32_t)u, false, false);
+  auto h = __builtin_amdgcn_permlane16_swap((uint32_t)(u >> 32), (uint32_t)(u >> 32), false, false);
+  v = __builtin_bit_cast(double, (uint64_t)l[0] | ((uint64_t)h[0] << 32)) +
+      __builtin_bit_cast(double, (uint64_t)l[1] | ((uint64_t)h[1] << 32));
+  u = __builtin_bit_cast(uint64_t, v);
+  l = __builtin_amdgcn_permlane32_swap((uint32_t)u, (uint32_t)u, false, false);
+  h = __builtin_amdgcn_permlane32_swap((uint32_t)(u >> 32), (uint32_t)(u >> 32), false, false);
+  return __builtin_bit_cast(double, (uint64_t)l[0] | ((uint64_t)h[0] << 32)) +
+         __builtin_bit_cast(double, (uint64_t)l[1] | ((uint64_t)h[1] << 32));
+}
+__device__ __forceinline__ uint32_t quad_or(uint32_t v) {
+  auto a = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+  v = a[0] | a[1];
+  auto b = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+  return b[0] | b[1];
 }
 
 // ---------------------------------------------------------------- operand formats

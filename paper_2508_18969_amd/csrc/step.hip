@@ -77,6 +77,10 @@ template <class Op_, int CB_, int NW_, int H1_, int H2_, int H3_> struct Cfg {
   // The LDS tail holds the GELU table (tabulated form only), then the
   // output-layer weights, copied once per workgroup when they fit.
   static constexpr int W4_BYTES = R4 * NQ4 * 64 * FRAG;
+  // bytes of packed layer l (row-blocks x k-steps x 64 lane fragments)
+  static constexpr int wbytes(int l) {
+    return (l == 0 ? R1 * NQ1 : l == 1 ? R2 * NQ2 : l == 2 ? R3 * NQ3 : R4 * NQ4) * 64 * FRAG;
+  }
   static constexpr int TAB_BYTES = GTAB_N * 16;
   static constexpr int LDS_TAIL = LDS_A2 + A2_BYTES;
   static constexpr int lds_w4(bool gt) { return LDS_TAIL + (gt ? TAB_BYTES : 0); }
@@ -86,8 +90,17 @@ template <class Op_, int CB_, int NW_, int H1_, int H2_, int H3_> struct Cfg {
   static_assert(lds_bytes(true) <= 160 * 1024, "LDS budget");
 };
 
-// Pointer into global memory: loads through it are global (not flat) loads.
-typedef const __attribute__((address_space(1))) uint8_t *gptr;
+// Weight fragments are read through buffer resources: the address of a load
+// is the resource base, one per-lane byte offset (a single VGPR for the whole
+// kernel) and a wave-uniform byte offset in an SGPR, so a load costs no
+// vector address arithmetic and keeps no 64-bit addresses live.  Loads past
+// num_records return zero instead of touching memory.
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+// word 3 of a raw (stride 0) gfx9 buffer resource: 32-bit data format
+constexpr int kBufWord3 = 0x00020000;
+__device__ __forceinline__ rsrc_t weight_rsrc(const void *p, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, bytes, kBufWord3);
+}
 
 // Workgroup barrier for LDS traffic only: unlike __syncthreads it does not
 // wait for outstanding global loads, so weight loads stay in flight.
@@ -95,20 +108,21 @@ __device__ __forceinline__ void lds_barrier() {
   asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
+// Fragment idx of a packed weight matrix (blocks of 64 lane fragments);
+// voff = lane * sizeof(frag_t).
 template <class frag_t>
-__device__ __forceinline__ frag_t ldg_frag(gptr base, int idx, int lane) {
-  gptr blk = base + (size_t)idx * (64 * sizeof(frag_t));
-  return *(const __attribute__((address_space(1))) frag_t *)(blk + (uint32_t)(lane * sizeof(frag_t)));
-}
-// The same load, kept at its place in the program: the block address passes
-// through an empty volatile asm statement, which the optimisers neither move
-// across the scheduling barriers nor see through, so the load can not be
-// hoisted ahead of the matrix products it is meant to follow.
-template <class frag_t>
-__device__ __forceinline__ frag_t ldg_frag_here(gptr base, int idx, int lane) {
-  gptr blk = base + (size_t)idx * (64 * sizeof(frag_t));
-  asm volatile("" : "+s"(blk));
-  return *(const __attribute__((address_space(1))) frag_t *)(blk + (uint32_t)(lane * sizeof(frag_t)));
+__device__ __forceinline__ frag_t ldb_frag(rsrc_t r, int idx, int voff) {
+  const int soff = idx * (64 * (int)sizeof(frag_t));
+  if constexpr (sizeof(frag_t) == 16) {
+    return __builtin_bit_cast(frag_t, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+  } else {
+    static_assert(sizeof(frag_t) == 32, "fragment size");
+    typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+    typedef uint32_t u8v __attribute__((ext_vector_type(8)));
+    const u4 lo = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+    const u4 hi = __builtin_amdgcn_raw_buffer_load_b128(r, voff + 16, soff, 0);
+    return __builtin_bit_cast(frag_t, u8v{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]});
+  }
 }
 template <class frag_t>
 __device__ __forceinline__ frag_t lds_frag(const uint8_t *base, int idx, int lane) {
@@ -116,6 +130,20 @@ __device__ __forceinline__ frag_t lds_frag(const uint8_t *base, int idx, int lan
 }
 
 __device__ __forceinline__ float umaxf(float a, float b) { return a > b ? a : b; }
+
+// A copy of a uniform value that the optimisers can not see through: offsets
+// derived from it are recomputed where they are used (one scalar add each)
+// instead of being precomputed for every load of a loop and spilled.
+__device__ __forceinline__ int opaque(int v) {
+  asm volatile("" : "+s"(v));
+  return v;
+}
+// The same for a per-lane value: LDS addresses built on it keep their
+// constant parts in the instruction's offset field.
+__device__ __forceinline__ int opaque_v(int v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
 
 template <class C, bool CALIB, bool GT>
 __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
@@ -193,11 +221,13 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
 
   for (int64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
     const int64_t cell0 = tile * C::MC;
-    // Opaque copies of the weight bases: address arithmetic is redone per tile
+    // Opaque copies of the weight bases: the resources are rebuilt per tile
     // instead of being hoisted out of the tile loop and kept live (spilled).
     const uint8_t *W1o = W1g, *W2o = W2g, *W3o = W3g, *W4o = W4g;
     asm volatile("" : "+s"(W1o), "+s"(W2o), "+s"(W3o), "+s"(W4o));
-    gptr W1 = (gptr)W1o, W2 = (gptr)W2o, W3 = (gptr)W3o, W4 = (gptr)W4o;
+    const rsrc_t W1 = weight_rsrc(W1o, C::wbytes(0)), W2 = weight_rsrc(W2o, C::wbytes(1));
+    const rsrc_t W3 = weight_rsrc(W3o, C::wbytes(2)), W4 = weight_rsrc(W4o, C::wbytes(3));
+    const int voff = lane * (int)sizeof(frag_t);
 
     // ------------------------------------------------------------ preprocess
     // Lane (cell 16w + cl, group g) computes input features f = 16h + 4g + r.
@@ -209,17 +239,18 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
       for (int h = 0; h < 2; ++h)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
+          // selects instead of branches: feature f is T or P only in the
+          // first two slots of the lanes with g == 0
           const int f = 16 * h + 4 * g + r;
           const double x = xin[4 * h + r];
-          float z = 0.0f;
-          if (valid) {
-            if (f == 0)
-              z = (float)((x - dcl[DConst::T_MU]) * dcl[DConst::T_IS]);
-            else if (f == 1)
-              z = (float)((x - dcl[DConst::P_MU]) * dcl[DConst::P_IS]);
-            else if (f - 2 < a.S)
-              z = __builtin_fmaf(ypow(x, lam), fcl[FConst::ZA + f], fcl[FConst::ZC + f]);
+          float z = __builtin_fmaf(ypow(x, lam), fcl[FConst::ZA + f], fcl[FConst::ZC + f]);
+          z = f - 2 < a.S ? z : 0.0f;
+          if (h == 0 && r < 2) {
+            const float ztp = r == 0 ? (float)((x - dcl[DConst::T_MU]) * dcl[DConst::T_IS])
+                                     : (float)((x - dcl[DConst::P_MU]) * dcl[DConst::P_IS]);
+            z = g == 0 ? ztp : z;
           }
+          z = valid ? z : 0.0f;
           if (CALIB) amx[0] = umaxf(amx[0], __builtin_fabsf(z));
           v[h][r] = z * inv_sa[0];
         }
@@ -249,6 +280,7 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
     const bool l1wave = C::NW == L1W || w < L1W;
     f4 acc1[C::RB1W][CB];
     f4 y1[C::RB1W][CB];
+    int wo = w;                                        // opaque copy, renewed per k-step
     auto layer1_mma = [&](int sc, const frag_t (&w1f)[C::NW1]) {
       if (!l1wave) return;
       // the input fragments, re-read per chunk (cheaper than keeping them
@@ -260,7 +292,7 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
         for (int cb = 0; cb < CB; ++cb) a0[q][cb] = lds_frag<frag_t>(A0, q * CB + cb, lane);
 #pragma unroll
       for (int ii = 0; ii < C::RB1W; ++ii) {
-        const f4 bias = *(const f4 *)(B1 + 16 * (sc * (C::SC / 16) + w * C::RB1W + ii) + 4 * g);
+        const f4 bias = *(const f4 *)(B1 + 16 * (sc * (C::SC / 16) + wo * C::RB1W + ii) + 4 * g);
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) {
           acc1[ii][cb] = Op::SCALED ? f4{0.f, 0.f, 0.f, 0.f} : bias;
@@ -272,12 +304,12 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
     // activation values [v0, v1) of chunk sc; a tile is stored with its last value
     auto layer1_act = [&](int sc, int buf, int v0, int v1) {
       if (!l1wave) return;
-      uint8_t *dst = A1 + buf * C::QSC * C::QBYTES;
+      const int dv = opaque_v(buf * C::QSC * C::QBYTES + lane * FRAG);
 #pragma unroll
       for (int v = 0; v < NV1; ++v) {
         if (v < v0 || v >= v1) continue;
         const int ii = v / (4 * CB), cb = (v / 4) % CB, r = v % 4;
-        const int rbl = w * C::RB1W + ii;              // row-block within the chunk
+        const int rbl = wo * C::RB1W + ii;             // row-block within the chunk
         const int rb = sc * (C::SC / 16) + rbl;
         const float bias = B1[16 * rb + 4 * g + r];
         const float zz = Op::SCALED ? __builtin_fmaf(acc1[ii][cb][r], sout[0], bias) : acc1[ii][cb][r];
@@ -289,8 +321,62 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
             for (int k = 0; k < 4; ++k) amx[1] = umaxf(amx[1], __builtin_fabsf(y[k]));
           if (Op::SCALED) y *= inv_sa[1];
           const int q2l = rbl / RPQ, j0 = 4 * (rbl % RPQ);
-          Op::store4(dst + ((q2l * CB + cb) * 64 + lane) * FRAG + j0 * EB, y);
+          Op::store4((A1 + cb * 64 * FRAG) + (dv + (q2l * CB * 64 * FRAG + j0 * EB)), y);
         }
+      }
+    };
+
+    // The same activation (tanh form) in stages, spread over the layer-2
+    // fragment groups of the loop.  The operations form a stage-major list:
+    // operation k is stage k / NV1 of value k % NV1, so that two dependent
+    // operations are a whole stage apart (their latency is covered), and each
+    // group takes a few of them, placed between its matrix products, whose
+    // execution they overlap.
+    // (BF16 / FP16 operands; the FP32 and FP8 loops keep one activation block,
+    // measured faster there)
+    constexpr bool STAGED = !GT && KS == 32;
+    constexpr int NOPS1 = 8 * NV1;
+    float xs[NV1], ts[NV1];
+    auto layer1_ops = [&](int sc, int buf, int k0, int k1) {
+      if (!l1wave) return;
+      const int dv = opaque_v(buf * C::QSC * C::QBYTES + lane * FRAG);
+#pragma unroll
+      for (int k = 0; k < NOPS1; ++k) {
+        if (k < k0 || k >= k1) continue;
+        const int st = k / NV1, v = k % NV1;
+        const int ii = v / (4 * CB), cb = (v / 4) % CB, r = v % 4;
+        if (st == 0) {
+          if constexpr (Op::SCALED) {
+            const float bias = B1[16 * (sc * (C::SC / 16) + wo * C::RB1W + ii) + 4 * g + r];
+            xs[v] = __builtin_fmaf(acc1[ii][cb][r], sout[0], bias);
+          } else {
+            xs[v] = acc1[ii][cb][r];
+          }
+          ts[v] = xs[v] * xs[v];
+        } else if (st == 1) {
+          ts[v] = __builtin_fmaf(ts[v], kG3, kG1);
+        } else if (st == 2) {
+          ts[v] = xs[v] * ts[v];
+        } else if (st == 3) {
+          ts[v] = __builtin_amdgcn_exp2f(ts[v]);
+        } else if (st == 4) {
+          ts[v] = 1.0f + ts[v];
+        } else if (st == 5) {
+          ts[v] = __builtin_amdgcn_rcpf(ts[v]);
+        } else if (st == 6) {
+          ts[v] = xs[v] * ts[v];
+        } else if (r == 3) {
+          f4 y = {ts[v - 3], ts[v - 2], ts[v - 1], ts[v]};
+          if (CALIB && cell0 + 16 * cb + cl < a.n)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) amx[1] = umaxf(amx[1], __builtin_fabsf(y[j]));
+          if (Op::SCALED) y *= inv_sa[1];
+          const int rbl = wo * C::RB1W + ii;
+          const int q2l = rbl / RPQ, j0 = 4 * (rbl % RPQ);
+          Op::store4((A1 + cb * 64 * FRAG) + (dv + (q2l * CB * 64 * FRAG + j0 * EB)), y);
+        }
+        // keeps the operation in its group
+        asm volatile("" : "+v"(ts[v]));
       }
     };
 
@@ -318,8 +404,8 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
     constexpr int NA2 = CB + (S2::NREM > 0 ? S2::NREM : 1);
     frag_t wb[NB2][NW2];
     auto w2_load = [&](frag_t &dst, int i, int q) {
-      const int rb = i < S2::F ? w * S2::F + i : S2::rem_rb(w, i - S2::F);
-      dst = ldg_frag<frag_t>(W2, rb * C::NQ2 + (q < C::NQ2 ? q : C::NQ2 - 1), lane);
+      const int rb = i < S2::F ? wo * S2::F + i : S2::rem_rb(wo, i - S2::F);
+      dst = ldb_frag<frag_t>(W2, rb * C::NQ2 + (q < C::NQ2 ? q : C::NQ2 - 1), voff);
     };
     frag_t w1r[C::NW1];
     auto w1_load = [&](int c) {
@@ -329,8 +415,8 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
       for (int ii = 0; ii < C::RB1W; ++ii)
 #pragma unroll
         for (int q = 0; q < C::NQ1; ++q) {
-          const int rb = cs * (C::SC / 16) + w * C::RB1W + ii;
-          w1r[ii * C::NQ1 + q] = ldg_frag<frag_t>(W1, rb * C::NQ1 + q, lane);
+          const int rb = cs * (C::SC / 16) + wo * C::RB1W + ii;
+          w1r[ii * C::NQ1 + q] = ldb_frag<frag_t>(W1, rb * C::NQ1 + q, voff);
         }
     };
     w1_load(0);
@@ -345,25 +431,29 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
 
 #pragma nounroll
     for (int sc = 0; sc < C::NSC; ++sc) {
-      // Layer 1 of the next chunk follows the first fragment group's products
-      // (the last iteration recomputes chunk 0 into the idle buffer, which
-      // keeps the loop body uniform).  Measured: one block there is faster
-      // than spreading its activation values over the fragment groups.
+      // Layer 1 of the next chunk: its products follow the first fragment
+      // group's, its activation is spread over the later groups (staged form)
+      // or follows as one block (the last iteration recomputes chunk 0 into
+      // the idle buffer, which keeps the loop body uniform).
       const int nsc = (sc + 1 == C::NSC) ? 0 : sc + 1;
       const int nbuf = (sc + 1) & 1;
-      const uint8_t *src = A1 + (sc & 1) * C::QSC * C::QBYTES;
-      // the chunk's activation fragments, read once
+      const int sv = opaque_v((sc & 1) * C::QSC * C::QBYTES + lane * FRAG);
+      const int wa = opaque(w);
+      // the chunk's activation fragments, read once (constant offsets first,
+      // so that they land in the instructions' offset fields)
       frag_t act[C::QSC][NA2];
 #pragma unroll
       for (int ql = 0; ql < C::QSC; ++ql) {
 #pragma unroll
-        for (int cb = 0; cb < CB; ++cb) act[ql][cb] = lds_frag<frag_t>(src, ql * CB + cb, lane);
+        for (int cb = 0; cb < CB; ++cb) act[ql][cb] = *(const frag_t *)((A1 + (ql * CB + cb) * 64 * FRAG) + sv);
 #pragma unroll
-        for (int k = 0; k < S2::NREM; ++k) act[ql][CB + k] = lds_frag<frag_t>(src, ql * CB + S2::rem_cb(w, k), lane);
+        for (int k = 0; k < S2::NREM; ++k)
+          act[ql][CB + k] = *(const frag_t *)((A1 + ql * CB * 64 * FRAG) + (sv + S2::rem_cb(wa, k) * 64 * FRAG));
       }
 #pragma unroll
       for (int ql = 0; ql < C::QSC; ++ql) {
         const int q = sc * C::QSC + ql;
+        wo = opaque(w);
         frag_t(&wc)[NW2] = wb[ql % NB2];
         // the scheduling barriers keep each refill right behind the products
         // that read the fragment (the scheduler would otherwise sink the
@@ -378,10 +468,35 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
             acc2[S2::F * CB + k] = Op::mma(wc[i], act[ql][CB + k], acc2[S2::F * CB + k]);
           }
           w2_load(wc[i], i, q + NB2);
-          if (ql == 0 && i == 0) {
+          const int gi = ql * NW2 + i;                 // fragment group of the chunk
+          if (gi == 0) {
             layer1_mma(nsc, w1r);
             w1_load(sc + 2);
-            layer1_act(nsc, nbuf, 0, NV1);
+            if constexpr (!STAGED) layer1_act(nsc, nbuf, 0, NV1);
+          }
+          if constexpr (STAGED) {
+            // the activation's operations from the third group on (the
+            // layer-1 products have finished by then)
+            // operations in proportion to the group's products
+            constexpr int G0 = 2, MK = S2::F * CB + S2::NREM;     // products per k-step
+            auto mcum = [](int gq) {                   // products before group gq
+              const int qq = gq / NW2, ig = gq % NW2;
+              return qq * MK + (ig < S2::F ? ig * CB : S2::F * CB + (ig - S2::F));
+            };
+            constexpr int MT = C::QSC * MK - (G0 / NW2) * MK - (G0 % NW2 < S2::F ? (G0 % NW2) * CB : S2::F * CB + (G0 % NW2 - S2::F));
+            static_assert(C::QSC * NW2 > G0 && MT > 0, "fragment groups for the layer-1 activation");
+            if (gi >= G0) {
+              const int m0 = mcum(gi) - mcum(G0), m1 = m0 + (i < S2::F ? CB : 1);
+              const int k0 = m0 * NOPS1 / MT, k1 = m1 * NOPS1 / MT;
+              layer1_ops(nsc, nbuf, k0, k1);
+              // products and activation operations alternate
+              constexpr int PER = (NOPS1 + MT - 1) / MT + 1;
+#pragma unroll
+              for (int m = 0; m < (i < S2::F ? CB : 1); ++m) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x002, PER, 0);
+              }
+            }
           }
           __builtin_amdgcn_sched_barrier(0);
         }
@@ -398,7 +513,7 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
     frag_t w3b[NB3][NW3];
     auto w3_load = [&](frag_t &dst, int i, int q) {
       const int rb = i < S3::F ? w * S3::F + i : S3::rem_rb(w, i - S3::F);
-      dst = ldg_frag<frag_t>(W3, rb * C::NQ3 + q, lane);
+      dst = ldb_frag<frag_t>(W3, rb * C::NQ3 + q, voff);
     };
 #pragma unroll
     for (int i = 0; i < NW3; ++i) w3_load(w3b[0][i], i, 0);
@@ -570,7 +685,7 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
 #pragma unroll
           for (int q = 0; q < NQ4L; ++q)
             w4r[rb][q] = W4L ? lds_frag<frag_t>(smem + LW4, rb * C::NQ4 + q0 + q, lane)
-                             : ldg_frag<frag_t>(W4, rb * C::NQ4 + q0 + q, lane);
+                             : ldb_frag<frag_t>(W4, rb * C::NQ4 + q0 + q, voff);
 #pragma unroll
         for (int q = 0; q < NQ4L; ++q) {
           const frag_t af = lds_frag<frag_t>(A2, (q0 + q) * CB + w, lane);
@@ -598,11 +713,12 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
       for (int h = 0; h < 2; ++h)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
+          // every row is evaluated (no branches); rows that are not species
+          // take y = 0 and are zeroed at the end
           const int rho = 16 * h + 4 * g + r, s = rho - 2, j = 4 * h + r;
-          Y[j] = 0.0;
-          Yh[j] = 0.0;
-          if (s >= 0 && s < a.S) {
-            const double y = Yc[j];
+          const bool sp = s >= 0 && s < a.S;
+          {
+            const double y = sp ? Yc[j] : 0.0;
             Y[j] = y;
             bad |= !__builtin_isfinite(y);
             const float b = ypow(y, lam);
@@ -615,56 +731,52 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
             const bool small = b > 0.0f && __builtin_fabsf(t) <= 0.5f;
             const float u = 1.0f + t;
             // log2(1 + t) = log2(u) t / (u - 1) for the rounded u (exact when u == 1)
-            const float l1p = u == 1.0f ? t * kLog2e
-                                        : __builtin_amdgcn_logf(u) * (t * __builtin_amdgcn_rcpf(u - 1.0f));
+            // (both arms of each choice are computed and pinned, so that the
+            // choice is a select, not a branch)
+            float l1a = t * kLog2e, l1b = __builtin_amdgcn_logf(u) * (t * __builtin_amdgcn_rcpf(u - 1.0f));
             const float base = b + wv;
-            const float z = (small ? l1p : __builtin_amdgcn_logf(base)) * inv_lam;
+            float lb = __builtin_amdgcn_logf(base);
+            asm volatile("" : "+v"(l1a), "+v"(l1b), "+v"(lb));
+            const float z = (small ? (u == 1.0f ? l1a : l1b) : lb) * inv_lam;
             const float e = __builtin_amdgcn_exp2f(z);
             // 2^z - 1 = (e - 1) z / log2(e) for the rounded e = 2^z
-            const float em1 = e == 1.0f ? z * kLn2 : (e - 1.0f) * (z * __builtin_amdgcn_rcpf(__builtin_amdgcn_logf(e)));
-            const double dy = small ? y * (double)em1 : (base > 0.0f ? (double)e : 0.0) - y;
+            float ema = z * kLn2, emb = (e - 1.0f) * (z * __builtin_amdgcn_rcpf(__builtin_amdgcn_logf(e)));
+            asm volatile("" : "+v"(ema), "+v"(emb));
+            const float em1 = e == 1.0f ? ema : emb;
+            double dys = y * (double)em1, dyl = (base > 0.0f ? (double)e : 0.0) - y;
+            asm volatile("" : "+v"(dys), "+v"(dyl));
+            const double dy = small ? dys : dyl;
             double yh = y + dy;
-            yh = yh > 0.0 ? yh : 0.0;
+            yh = sp && yh > 0.0 ? yh : 0.0;
             Yh[j] = yh;
             ssum += yh;
-            if (a.thermo) h0 += y * (dcl[DConst::HF + rho] + dcl[DConst::CP + rho] * (T - t_ref));
+            // (the tables are zero past the species rows and without thermo data)
+            h0 += y * (dcl[DConst::HF + rho] + dcl[DConst::CP + rho] * (T - t_ref));
           }
         }
       // the cell's four lanes: l, l^16, l^32, l^48
-      ssum += __shfl_xor(ssum, 16);
-      ssum += __shfl_xor(ssum, 32);
-      int badi = bad ? 1 : 0;
-      badi |= __shfl_xor(badi, 16);
-      badi |= __shfl_xor(badi, 32);
+      ssum = quad_sum(ssum);
       double Yn[8];
       double hn = 0.0, cn = 0.0;
       const double rsum = 1.0 / ssum;
+      uint32_t nonfin = 0u;
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         Yn[j] = Yh[j] * rsum;
+        nonfin |= __builtin_isfinite(Yn[j]) ? 0u : 1u;
         const int rho = 16 * (j >> 2) + 4 * g + (j & 3);
-        if (a.thermo && rho >= 2 && rho - 2 < a.S) {
-          hn += Yn[j] * dcl[DConst::HF + rho];
-          cn += Yn[j] * dcl[DConst::CP + rho];
-        }
+        hn += Yn[j] * dcl[DConst::HF + rho];
+        cn += Yn[j] * dcl[DConst::CP + rho];
       }
       double Tn = T;
       if (a.thermo) {
-        h0 += __shfl_xor(h0, 16);
-        h0 += __shfl_xor(h0, 32);
-        hn += __shfl_xor(hn, 16);
-        hn += __shfl_xor(hn, 32);
-        cn += __shfl_xor(cn, 16);
-        cn += __shfl_xor(cn, 32);
+        h0 = quad_sum(h0);
+        hn = quad_sum(hn);
+        cn = quad_sum(cn);
         Tn = t_ref + (h0 - hn) / cn;
       }
-      bool okc = !badi && ssum > 0.0 && __builtin_isfinite(ssum) && __builtin_isfinite(Tn);
-      int fin = 1;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) fin &= __builtin_isfinite(Yn[j]) ? 1 : 0;
-      fin &= __shfl_xor(fin, 16);
-      fin &= __shfl_xor(fin, 32);
-      okc = okc && fin;
+      const uint32_t badq = quad_or((bad ? 1u : 0u) | nonfin);
+      const bool okc = !badq && ssum > 0.0 && __builtin_isfinite(ssum) && __builtin_isfinite(Tn);
       if (valid) {
 #pragma unroll
         for (int h = 0; h < 2; ++h)
