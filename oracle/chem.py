@@ -242,6 +242,33 @@ def step(T, P, Y, net, fmt=None, act_scale=None, w_scale=None, thermo=None, act=
     return {"Y_new": ynew, "T_new": tnew, "o": o, "bad": bad}
 
 
+# Molar gas constant, J/(mol K) (exact in the SI since 2019: N_A k_B).
+R_GAS = 8.31446261815324
+
+
+def mixture_density(T, P, Y, W):
+    """Ideal-gas density (kg/m^3) of cells at T (K) and P (Pa) with mass
+    fractions Y [S][n] and species molar masses W [S] (kg/mol):
+    rho = P / (R T sum_s Y_s / W_s).  (The flame of the paper is
+    supercritical and takes rho from a property network; the ideal-gas law
+    is the reading used here.)"""
+    T = np.asarray(T, dtype=np.float64)
+    P = np.asarray(P, dtype=np.float64)
+    Y = np.asarray(Y, dtype=np.float64)
+    W = np.asarray(W, dtype=np.float64)
+    return P / (R_GAS * T * np.sum(Y / W[:, None], axis=0))
+
+
+def source_terms(T, P, Y, Y_new, W, dt):
+    """Chemical source terms of the species transport equations, the
+    quantity the network's result stands for (Sec. 2, DeepFlame workflow):
+    omega_s = rho (Y_new,s - Y_s) / dt in kg/(m^3 s), rho the ideal-gas
+    density of the state before the step.  Cells passed through by the step
+    (Y_new = Y) get 0."""
+    rho = mixture_density(T, P, Y, W)
+    return rho[None, :] * (np.asarray(Y_new, np.float64) - np.asarray(Y, np.float64)) / float(dt)
+
+
 def layer_input_amax(T, P, Y, net):
     """Per-layer max |input| of the exact FP64 forward over a calibration set."""
     z = features(T, P, Y, net.in_mean, net.in_std, net.lam)

@@ -304,6 +304,15 @@ def make_thermo(config: int, S: int):
     return hf, cp, 298.15
 
 
+def make_molar_masses(config: int, S: int) -> np.ndarray:
+    """Species molar masses [S] in kg/mol, log-uniform on [2e-3, 2e-1] (from
+    hydrogen to heavy hydrocarbons); drawn after make_thermo's values on the
+    same stream."""
+    rng = streams(config)["extra"]
+    rng.uniform(size=2 * S)                      # the thermo table's draws
+    return np.exp(rng.uniform(np.log(2e-3), np.log(2e-1), size=S))
+
+
 # --------------------------------------------------------------------------- mechanism
 ATOMIC_MASS = np.array([12.011, 1.008, 15.999, 14.007]) * 1e-3   # kg/mol: C, H, O, N
 

@@ -299,3 +299,47 @@ def test_gelu_table_outside_and_jump():
     np.testing.assert_array_equal(chem.gelu_table(x), np.where(x < 0, 0.0, x))
     jump = abs(chem.gelu_table(-2.9999999) - chem.gelu_table(-3.0000001))
     assert abs(jump - abs(chem.gelu(-3.0))) <= 1e-6
+
+
+# ------------------------------------------------------------------ source terms
+def test_density_of_a_single_species_is_the_ideal_gas_law():
+    """One species: rho = P W / (R T); nitrogen at 300 K and 1 atm is
+    1.138 kg/m^3 (W = 28.0134 g/mol)."""
+    W = np.array([0.0280134, 0.0319988])
+    Y = np.array([[1.0], [0.0]])
+    rho = chem.mixture_density(np.array([300.0]), np.array([101325.0]), Y, W)
+    assert abs(rho[0] - 101325.0 * 0.0280134 / (8.31446261815324 * 300.0)) < 1e-12
+    assert abs(rho[0] - 1.138) < 5e-4
+
+
+def test_density_matches_the_mole_fraction_form():
+    """rho = P Wbar / (R T) with Wbar = sum_s x_s W_s and x_s the mole
+    fractions: another route to the same number."""
+    S, n = 9, 50
+    rng = np.random.default_rng(3)
+    W = rng.uniform(0.002, 0.2, S)
+    Y = rng.dirichlet(np.full(S, 0.5), n).T
+    T = rng.uniform(300, 3000, n)
+    P = rng.uniform(1e5, 2e7, n)
+    moles = Y / W[:, None]
+    x = moles / moles.sum(axis=0)
+    wbar = (x * W[:, None]).sum(axis=0)
+    np.testing.assert_allclose(chem.mixture_density(T, P, Y, W), P * wbar / (chem.R_GAS * T),
+                               rtol=1e-13)
+
+
+def test_source_terms_conserve_mass_and_scale_with_dt():
+    """sum_s omega_s = 0 when both states sum to one; omega is linear in the
+    change and inversely proportional to dt; a passed-through cell has none."""
+    net = synth.make_net(1)
+    st = synth.make_state(1, 300)
+    W = synth.make_molar_masses(1, 17)
+    out = chem.step(st.T, st.P, st.Y, net)
+    om = chem.source_terms(st.T, st.P, st.Y, out["Y_new"], W, 1e-6)
+    rho = chem.mixture_density(st.T, st.P, st.Y, W)
+    scale = rho / 1e-6
+    assert np.max(np.abs(om.sum(axis=0)) / scale) < 1e-14
+    om2 = chem.source_terms(st.T, st.P, st.Y, out["Y_new"], W, 2e-6)
+    np.testing.assert_allclose(om2, om / 2, rtol=1e-14, atol=0)
+    np.testing.assert_allclose(om * 1e-6 / rho, out["Y_new"] - st.Y, rtol=1e-12, atol=1e-18)
+    assert not np.any(chem.source_terms(st.T, st.P, st.Y, st.Y, W, 1e-6))
