@@ -16,6 +16,11 @@
  *   5. Yhat = Y + (Y* - Y) in FP64;  Y_new = Yhat / sum(Yhat)   (FP64, Sec. 3.3.1:
  *            everything outside the network stays in double precision)
  *   6. optional T_new keeping sum_s Y_s (h_f,s + c_p,s (T - T_ref)) constant.
+ *   7. optional (chem_dnn_step_source) species source terms
+ *            omega_s = rho (Y_new,s - Y_s) / dt, rho = P / (R T sum_s Y_s / W_s),
+ *            the chemical source terms the network's result stands for in the
+ *            species transport equations (Sec. 2, DeepFlame workflow); ideal-gas
+ *            density of the state before the step.
  *
  * Conventions for every entry point
  *   - Return value: CHEM_DNN_OK or a negative status; nothing throws or exits.
@@ -86,6 +91,8 @@ typedef struct {
     const double *thermo_cp;    /* [S] constant c_p J/(kg K); NULL iff thermo_hf is NULL */
     double t_ref;               /* reference temperature of h_f, K */
     int64_t max_batch;          /* largest batch of chem_dnn_train_step (0 = no training) */
+    const double *molar_mass;   /* [S] species molar masses kg/mol, > 0; NULL -> no source
+                                   terms (chem_dnn_step_source returns EINVAL) */
 } chem_dnn_desc;
 
 /* Bytes of device workspace chem_dnn_init needs for `desc` (packed weights,
@@ -119,6 +126,16 @@ int32_t chem_dnn_set_params(chem_dnn *h, const float *params, void *stream);
 int32_t chem_dnn_step(chem_dnn *h, int64_t n, int64_t ld, const double *T, const double *P,
                       const double *Y, double *Y_out, double *T_out, uint32_t *n_bad,
                       void *stream);
+
+/* chem_dnn_step plus the species source terms of step 7:
+ *   omega     device FP64 [S][ld]  kg/(m^3 s); must not alias T, P, Y, Y_out
+ *             or T_out.  0 for cells passed through as bad.
+ *   dt        the time step the network's change refers to, s, > 0 (finite)
+ * The other arguments are those of chem_dnn_step.  EINVAL if the handle was
+ * created without molar masses. */
+int32_t chem_dnn_step_source(chem_dnn *h, int64_t n, int64_t ld, const double *T,
+                             const double *P, const double *Y, double *Y_out, double *T_out,
+                             double *omega, double dt, uint32_t *n_bad, void *stream);
 
 /* FP8 calibration: running the FP32-operand network on n cells, writes each
  * layer's max |input| (device FP32 [L], overwritten) - the act_amax of an FP8
@@ -173,7 +190,8 @@ int32_t chem_dnn_destroy(chem_dnn *h);
 /* Static description of a status code. */
 const char *chem_dnn_strerror(int32_t status);
 
-/* ABI version of this header: 2 (2 added gelu_form to chem_dnn_desc). */
+/* ABI version of this header: 3 (2 added gelu_form to chem_dnn_desc; 3 added
+ * molar_mass at its end and chem_dnn_step_source). */
 int32_t chem_dnn_abi_version(void);
 
 #ifdef __cplusplus

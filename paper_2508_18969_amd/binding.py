@@ -20,7 +20,7 @@ OK, EINVAL, ENODEV, EWORKSPACE, EUNSUPPORTED, EHIP = 0, -1, -2, -3, -4, -5
 FP32, BF16, FP16, FP8E4M3 = 0, 1, 2, 3
 PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp16": FP16, "fp8": FP8E4M3}
 EXPORTS = ("chem_dnn_workspace_bytes", "chem_dnn_init", "chem_dnn_set_params", "chem_dnn_step",
-           "chem_dnn_calibrate", "chem_dnn_get_scales", "chem_dnn_mlp_forward",
+           "chem_dnn_step_source", "chem_dnn_calibrate", "chem_dnn_get_scales", "chem_dnn_mlp_forward",
            "chem_dnn_mlp_backward", "chem_dnn_train_step", "chem_dnn_destroy",
            "chem_dnn_strerror", "chem_dnn_abi_version")
 
@@ -33,7 +33,7 @@ class Desc(C.Structure):
                 ("precision", C.c_int32), ("gelu_form", C.c_int32), ("boxcox_lambda", C.c_double),
                 ("in_mean", _dp), ("in_std", _dp), ("out_mean", _dp), ("out_std", _dp),
                 ("act_amax", _fp), ("thermo_hf", _dp), ("thermo_cp", _dp), ("t_ref", C.c_double),
-                ("max_batch", C.c_int64)]
+                ("max_batch", C.c_int64), ("molar_mass", _dp)]
 
 
 class ChemDNNError(RuntimeError):
@@ -59,6 +59,7 @@ def lib():
         L.chem_dnn_init.argtypes = [C.POINTER(Desc), vp, vp, C.c_size_t, vp, C.POINTER(vp)]
         L.chem_dnn_set_params.argtypes = [vp, vp, vp]
         L.chem_dnn_step.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp, vp]
+        L.chem_dnn_step_source.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp, C.c_double, vp, vp]
         L.chem_dnn_calibrate.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp]
         L.chem_dnn_get_scales.argtypes = [vp, _fp, _fp, vp]
         L.chem_dnn_mlp_forward.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp]
@@ -129,7 +130,7 @@ GELU_FORMS = {"tanh": 0, "table": 1}
 
 
 def make_desc(widths, precision, in_mean, in_std, out_mean=None, out_std=None, act_amax=None,
-              thermo=None, max_batch=0, lam=0.1, gelu="tanh"):
+              thermo=None, max_batch=0, lam=0.1, gelu="tanh", molar_mass=None):
     """Fills a Desc; returns (desc, keepalive) - keep the second alive while the
     desc is in use."""
     d = Desc()
@@ -155,6 +156,10 @@ def make_desc(widths, precision, in_mean, in_std, out_mean=None, out_std=None, a
         keep += [a, b]
         d.thermo_hf, d.thermo_cp, d.t_ref = p, q, float(tref)
     d.max_batch = int(max_batch)
+    if molar_mass is not None:
+        a, p = _arr(molar_mass, C.c_double)
+        keep.append(a)
+        d.molar_mass = p
     return d, keep
 
 
@@ -172,7 +177,7 @@ class ChemDNN:
     """
 
     def __init__(self, widths, precision, params, in_mean, in_std, out_mean=None, out_std=None,
-                 act_amax=None, thermo=None, max_batch=0, lam=0.1, gelu="tanh"):
+                 act_amax=None, thermo=None, max_batch=0, lam=0.1, gelu="tanh", molar_mass=None):
         import torch
         self.widths = tuple(int(w) for w in widths)
         self.S = self.widths[-1]
@@ -180,7 +185,7 @@ class ChemDNN:
         self.precision = precision
         self.thermo = thermo is not None
         desc, keep = make_desc(self.widths, precision, in_mean, in_std, out_mean, out_std,
-                               act_amax, thermo, max_batch, lam, gelu)
+                               act_amax, thermo, max_batch, lam, gelu, molar_mass)
         nbytes = workspace_bytes(desc)
         dev = params.device
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
@@ -211,6 +216,27 @@ class ChemDNN:
         _check(lib().chem_dnn_step(self._h, n, ld, _ptr(T), _ptr(P), _ptr(Y), _ptr(Y_out),
                                    _ptr(T_out), _ptr(n_bad), _stream()), "chem_dnn_step")
         return Y_out, T_out
+
+    def step_source(self, T, P, Y, dt, Y_out=None, T_out=None, omega=None, n_bad=None):
+        """chem_dnn_step plus the species source terms omega [S][ld] (float64,
+        kg/(m^3 s)) of a step of dt seconds; needs molar_mass at construction."""
+        import torch
+        n = int(T.shape[0])
+        ld = int(Y.stride(0)) if Y.dim() == 2 else n
+        if Y_out is None:
+            Y_out = torch.empty_like(Y)
+        if T_out is None and self.thermo:
+            T_out = torch.empty_like(T)
+        if omega is None:
+            omega = torch.empty_like(Y)
+        f64 = torch.float64
+        for t, nm, r in ((T, "T", 1), (P, "P", 1), (Y, "Y", self.S), (Y_out, "Y_out", self.S),
+                         (T_out, "T_out", 1), (omega, "omega", self.S)):
+            _check_field(t, nm, r, n, ld, f64)
+        _check(lib().chem_dnn_step_source(self._h, n, ld, _ptr(T), _ptr(P), _ptr(Y), _ptr(Y_out),
+                                          _ptr(T_out), _ptr(omega), float(dt), _ptr(n_bad),
+                                          _stream()), "chem_dnn_step_source")
+        return Y_out, T_out, omega
 
     def calibrate(self, T, P, Y):
         """Per-layer input max |a| (CUDA float32 [L]) for an FP8 description."""

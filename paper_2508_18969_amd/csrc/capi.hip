@@ -29,6 +29,7 @@ struct chem_dnn {
   TrainScratch tr;
   int64_t max_batch;
   int thermo;
+  int molar;       // molar masses given: source terms available
   int gelu_form;
   float *gtab;
   // host copies kept alive for the asynchronous uploads
@@ -85,6 +86,9 @@ int32_t check_desc(const chem_dnn_desc *d) {
   if ((d->thermo_hf == nullptr) != (d->thermo_cp == nullptr)) return CHEM_DNN_EINVAL;
   if (d->precision == CHEM_DNN_FP8E4M3 && !d->act_amax) return CHEM_DNN_EINVAL;
   if (d->max_batch < 0) return CHEM_DNN_EINVAL;
+  if (d->molar_mass)
+    for (int s = 0; s < S; ++s)
+      if (!(d->molar_mass[s] > 0.0) || !isfinite(d->molar_mass[s])) return CHEM_DNN_EINVAL;
   if (L != 4) return CHEM_DNN_EUNSUPPORTED;
   return CHEM_DNN_OK;
 }
@@ -173,6 +177,8 @@ StepArgs step_args(chem_dnn *h, int64_t n, int64_t ld, const double *T, const do
   a.fc = h->fc; a.dc = h->dc;
   a.amax = nullptr;
   a.gtab = h->gtab;
+  a.omega = nullptr;
+  a.inv_dt = 0.0;
   a.S = h->S;
   a.thermo = h->thermo;
   return a;
@@ -187,7 +193,7 @@ int grid_for(const chem_dnn *h, int64_t ntiles) {
 
 extern "C" {
 
-int32_t chem_dnn_abi_version(void) { return 2; }
+int32_t chem_dnn_abi_version(void) { return 3; }
 
 const char *chem_dnn_strerror(int32_t st) {
   switch (st) {
@@ -252,6 +258,7 @@ int32_t chem_dnn_init(const chem_dnn_desc *d, const float *params, void *workspa
   h->max_batch = d->max_batch;
   train_scratch_layout(&h->tr, h->ws + p.train, d->widths, d->max_batch);
   h->thermo = d->thermo_hf ? 1 : 0;
+  h->molar = d->molar_mass ? 1 : 0;
   h->gelu_form = d->gelu_form;
   fill_gelu_table(h->hgtab);
 
@@ -272,6 +279,7 @@ int32_t chem_dnn_init(const chem_dnn_desc *d, const float *params, void *workspa
       h->hdc[DConst::HF + f] = d->thermo_hf[s];
       h->hdc[DConst::CP + f] = d->thermo_cp[s];
     }
+    if (d->molar_mass) h->hdc[DConst::WINV + f] = 1.0 / d->molar_mass[s];
   }
   for (int l = 0; l < 4; ++l) {
     const double sa = (h->prec == CHEM_DNN_FP8E4M3) ? act_scale_of(d->act_amax[l]) : 1.0;
@@ -324,6 +332,23 @@ int32_t chem_dnn_step(chem_dnn *h, int64_t n, int64_t ld, const double *T, const
   if (!T || !P || !Y || !Y_out) return CHEM_DNN_EINVAL;
   if (T_out && !h->thermo) return CHEM_DNN_EINVAL;
   StepArgs a = step_args(h, n, ld, T, P, Y, Y_out, T_out, n_bad);
+  auto launch = h->gelu_form == CHEM_DNN_GELU_TABLE ? h->lay.step_tab : h->lay.step;
+  return hip_status(launch(a, grid_for(h, a.ntiles), (hipStream_t)stream));
+}
+
+int32_t chem_dnn_step_source(chem_dnn *h, int64_t n, int64_t ld, const double *T,
+                             const double *P, const double *Y, double *Y_out, double *T_out,
+                             double *omega, double dt, uint32_t *n_bad, void *stream) {
+  if (!h || n < 0 || ld < n) return CHEM_DNN_EINVAL;
+  if (!h->molar || !(dt > 0.0) || !isfinite(dt)) return CHEM_DNN_EINVAL;
+  if (n == 0) return CHEM_DNN_OK;
+  if (!T || !P || !Y || !Y_out || !omega) return CHEM_DNN_EINVAL;
+  if (T_out && !h->thermo) return CHEM_DNN_EINVAL;
+  const void *o = omega;
+  if (o == T || o == P || o == Y || o == Y_out || o == T_out) return CHEM_DNN_EINVAL;
+  StepArgs a = step_args(h, n, ld, T, P, Y, Y_out, T_out, n_bad);
+  a.omega = omega;
+  a.inv_dt = 1.0 / dt;
   auto launch = h->gelu_form == CHEM_DNN_GELU_TABLE ? h->lay.step_tab : h->lay.step;
   return hip_status(launch(a, grid_for(h, a.ntiles), (hipStream_t)stream));
 }

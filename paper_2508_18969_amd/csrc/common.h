@@ -38,6 +38,8 @@ typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 // correct limits 0 and x for large |x|.
 constexpr double kSqrt2OverPi = 0.7978845608028654;
 constexpr double kGeluCubic = 0.044715;
+// Molar gas constant, J/(mol K) (exact in the SI: N_A k_B).
+constexpr double kRGas = 8.31446261815324;
 constexpr float kLog2e = 1.4426950408889634f;
 constexpr float kLn2 = 0.6931471805599453f;
 constexpr float kG1 = (float)(-2.0 * kSqrt2OverPi * 1.4426950408889634);

@@ -31,7 +31,8 @@ struct DConst {
     T_MU = 0, T_IS = 1, P_MU = 2, P_IS = 3, T_REF = 4, LAM = 5,
     HF = 8,    // [32] by output row rho = s + 2
     CP = 40,   // [32]
-    N = 72
+    WINV = 72, // [32] 1 / molar mass, mol/kg, by output row (0 past the species)
+    N = 104
   };
 };
 
@@ -46,6 +47,8 @@ struct StepArgs {
   const double *dc;      // DConst block
   float *amax;           // calibration output [4] (bit pattern max)
   const float *gtab;     // tabulated GELU: [GTAB_N][4] (c0, c1, c2, 0) per interval
+  double *omega;         // species source terms [S][ld], or NULL
+  double inv_dt;         // 1 / dt of the source terms
   int S, thermo;
 };
 

@@ -777,13 +777,25 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
       }
       const uint32_t badq = quad_or((bad ? 1u : 0u) | nonfin);
       const bool okc = !badq && ssum > 0.0 && __builtin_isfinite(ssum) && __builtin_isfinite(Tn);
+      // species source terms: ideal-gas density of the state before the step
+      double rho_dt = 0.0;
+      if (a.omega) {
+        double ry = 0.0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) ry += Y[j] * dcl[DConst::WINV + 16 * (j >> 2) + 4 * g + (j & 3)];
+        ry = quad_sum(ry);
+        rho_dt = okc ? P / (kRGas * T * ry) * a.inv_dt : 0.0;
+      }
       if (valid) {
 #pragma unroll
         for (int h = 0; h < 2; ++h)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int s = 16 * h + 4 * g + r - 2, j = 4 * h + r;
-            if (s >= 0 && s < a.S) __builtin_nontemporal_store(okc ? Yn[j] : Y[j], &a.Y_out[(int64_t)s * a.ld + i]);
+            if (s >= 0 && s < a.S) {
+              __builtin_nontemporal_store(okc ? Yn[j] : Y[j], &a.Y_out[(int64_t)s * a.ld + i]);
+              if (a.omega) __builtin_nontemporal_store(okc ? rho_dt * (Yn[j] - Y[j]) : 0.0, &a.omega[(int64_t)s * a.ld + i]);
+            }
           }
         if (g == 0) {
           if (a.T_out) __builtin_nontemporal_store(okc ? Tn : T, &a.T_out[i]);

@@ -27,7 +27,7 @@ def test_header_declares_what_the_library_exports(L):
     lib = L.lib()
     for name in decl:
         assert hasattr(lib, name), name
-    assert lib.chem_dnn_abi_version() == 2
+    assert lib.chem_dnn_abi_version() == 3
     for st in (0, -1, -2, -3, -4, -5):
         assert L.strerror(st) and L.strerror(st) != "unknown status"
 
@@ -51,7 +51,8 @@ def test_workspace_bytes_and_validation(L):
            dict(precision=7),
            dict(in_std=np.zeros(19)),
            dict(precision="fp8"),                          # FP8 needs act_amax
-           dict(gelu=2)]                                   # no such activation form
+           dict(gelu=2),                                   # no such activation form
+           dict(molar_mass=-np.ones(17))]                  # molar masses must be positive
     for kw in bad:
         d3, k3 = _desc(L, **kw)
         with pytest.raises(L.ChemDNNError) as e:
@@ -66,6 +67,8 @@ def test_workspace_bytes_and_validation(L):
 def test_entry_points_reject_null_handles(L):
     lib = L.lib()
     assert lib.chem_dnn_step(None, 10, 10, None, None, None, None, None, None, None) == L.EINVAL
+    assert lib.chem_dnn_step_source(None, 10, 10, None, None, None, None, None, None, 1e-6, None,
+                                    None) == L.EINVAL
     assert lib.chem_dnn_destroy(None) == L.EINVAL
     assert lib.chem_dnn_set_params(None, None, None) == L.EINVAL
     assert lib.chem_dnn_train_step(None, 1, 1, None, None, None, None, None, None, None, None, 1,

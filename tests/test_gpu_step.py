@@ -212,6 +212,62 @@ def test_gelu_table_bf16_matches_emulation():
     assert rg.max() <= 0.5 * re.max()
 
 
+# ------------------------------------------------------------------ source terms
+@pytest.mark.parametrize("config,n", [(1, 4096 + 5), (2, 2053)])
+def test_source_terms_match_oracle(config, n):
+    """FP32: omega against the oracle's source terms of its own step.  omega dt
+    / rho is Y_new - Y, so the bar is that of Y_new (1e-5 relative).  Y_out and
+    T_out are those of chem_dnn_step, bit for bit."""
+    _note(f"case source terms config={config} n={n}")
+    net = synth.make_net(config)
+    S = 17 if config == 1 else 29
+    thermo = synth.make_thermo(config, S)
+    W = synth.make_molar_masses(config, S)
+    st = synth.make_state(config, n)
+    h = make_handle(net, "fp32", thermo=thermo, molar_mass=W)
+    T, P, Y = dev_state(st)
+    dt = 1e-6
+    Yo, To, om = h.step_source(T, P, Y, dt)
+    Y2, T2 = h.step(T, P, Y)
+    torch.cuda.synchronize()
+    assert torch.equal(Yo, Y2) and torch.equal(To, T2)
+    ref = chem.step(st.T, st.P, st.Y, net, thermo=thermo)
+    om_ref = chem.source_terms(st.T, st.P, st.Y, ref["Y_new"], W, dt)
+    rho = chem.mixture_density(st.T, st.P, st.Y, W)
+    omg = om.cpu().numpy()
+    e = np.abs(omg - om_ref) * dt / rho[None, :]
+    bound = 1e-5 * np.maximum(np.abs(ref["Y_new"]), 1e-10)
+    _note(f"  max |d omega| dt/rho / bound = {np.max(e / bound):.3f}")
+    assert np.all(e <= bound)
+    # mass conservation of the exported terms, relative to rho / dt
+    assert np.max(np.abs(omg.sum(axis=0)) * dt / rho) < 1e-12
+
+
+def test_source_terms_narrow_and_bad_cells():
+    """BF16: omega is the GPU's own Y change times rho / dt; cells passed
+    through as bad get zero source terms."""
+    _note("case source terms bf16 + bad cells")
+    net = synth.make_net(2)
+    thermo = synth.make_thermo(2, 29)
+    W = synth.make_molar_masses(2, 29)
+    st = synth.make_state(2, 1000)
+    st.T[7] = np.nan
+    st.Y[3, 11] = np.inf
+    h = make_handle(net, "bf16", thermo=thermo, molar_mass=W)
+    T, P, Y = dev_state(st)
+    nb = torch.zeros(1, dtype=torch.int32, device="cuda")
+    Yo, To, om = h.step_source(T, P, Y, 2e-6, n_bad=nb)
+    torch.cuda.synchronize()
+    assert int(nb.item()) == 2
+    omg, yo = om.cpu().numpy(), Yo.cpu().numpy()
+    assert not np.any(omg[:, [7, 11]])
+    ok = np.ones(1000, bool)
+    ok[[7, 11]] = False
+    rho = chem.mixture_density(st.T[ok], st.P[ok], st.Y[:, ok], W)
+    np.testing.assert_allclose(omg[:, ok] * 2e-6 / rho[None, :], yo[:, ok] - st.Y[:, ok],
+                               rtol=1e-12, atol=1e-18)
+
+
 # ------------------------------------------------------------------ properties
 def test_cells_are_independent_and_runs_deterministic():
     _note("case independence bf16")
