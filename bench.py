@@ -64,7 +64,8 @@ def main():
     ap.add_argument("--precisions", default="fp32,bf16,fp16,fp8,bf16+table",
                     help="'+table' selects the tabulated GELU")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline leg")
-    ap.add_argument("--workloads", default="fp8_bimodal_2p24,block_2p27,train_b65536",
+    ap.add_argument("--workloads",
+                    default="fp8_bimodal_2p24,block_2p27,train_b65536,source_2p20,odenet_2p20",
                     help="further workloads timed after the headline one ('' for none)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="bytes of one plain device copy run before the timed region")
@@ -342,7 +343,72 @@ def wl_train(torch, synth, ChemDNN, B=65536, steps=20):
     return out, None
 
 
-WORKLOADS = {"fp8_bimodal_2p24": wl_fp8_bimodal, "block_2p27": wl_block, "train_b65536": wl_train}
+def wl_source(torch, synth, ChemDNN, n=1 << 20, dt=1e-6):
+    """The headline batch (2^20 cells, 29 species) through chem_dnn_step_source
+    in BF16: the update plus the species source terms rho (Y_new - Y)/dt, with
+    seeded molar masses (232 more bytes written per cell)."""
+    net = synth.make_net(2)
+    thermo = synth.make_thermo(2, 29)
+    W = synth.make_molar_masses(2, 29)
+    st = synth.make_state(2, n)
+    dev = torch.device("cuda")
+    T, P, Y = (torch.tensor(a, device=dev) for a in (st.T, st.P, st.Y))
+    Yo, To, om = torch.empty_like(Y), torch.empty_like(T), torch.empty_like(Y)
+    params = torch.tensor(net.flat_params(), device=dev)
+    h = ChemDNN(net.widths, "bf16", params, net.in_mean, net.in_std, net.out_mean, net.out_std,
+                thermo=thermo, lam=net.lam, molar_mass=W)
+    for _ in range(3):
+        h.step_source(T, P, Y, dt, Y_out=Yo, T_out=To, omega=om)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        h.step_source(T, P, Y, dt, Y_out=Yo, T_out=To, omega=om)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 10
+    h.close()
+    out = {"bf16": _rate(n, ms, "bf16")}
+    out["bf16"]["state_GBps"] = (STATE_BYTES_PER_CELL + 8 * 29) * n / (ms * 1e-3) * 1e-9
+    out["config"] = {"cells": n, "dt_s": dt, "molar_mass": "log-uniform 2-200 g/mol",
+                     "density": "ideal gas of the state before the step"}
+    del T, P, Y, Yo, To, om
+    torch.cuda.empty_cache()
+    return out, None
+
+
+def wl_odenet(torch, synth, ChemDNN, n=1 << 20):
+    """The ODENet size of the paper's runs, 19-2048-4096-2048-1024-512-17
+    (38.9 MFLOP per cell), over 2^20 cells of the 17-species distribution, in
+    BF16 and FP16 on the layer-by-layer path (chunks of 32,768 cells, one
+    matrix-core kernel per layer)."""
+    net = synth.make_net(6)
+    thermo = synth.make_thermo(6, 17)
+    st = synth.make_state(6, n)
+    dev = torch.device("cuda")
+    T, P, Y = (torch.tensor(a, device=dev) for a in (st.T, st.P, st.Y))
+    Yo, To = torch.empty_like(Y), torch.empty_like(T)
+    params = torch.tensor(net.flat_params(), device=dev)
+    flop = 2 * sum(a * b for a, b in zip(net.widths[:-1], net.widths[1:]))
+    out = {}
+    for prec in ("bf16", "fp16"):
+        h = ChemDNN(net.widths, prec, params, net.in_mean, net.in_std, net.out_mean, net.out_std,
+                    thermo=thermo, lam=net.lam)
+        ms = _time_steps(torch, h, T, P, Y, Yo, To, 3, 1)
+        h.close()
+        tf = flop * n / (ms * 1e-3) * 1e-12
+        out[prec] = {"ms_per_step": ms, "cells_per_s": n / (ms * 1e-3), "tflops": tf,
+                     "mfma_frac": tf / PEAK_TFLOPS[prec]}
+    out["config"] = {"cells": n, "widths": list(net.widths), "flop_per_cell": flop,
+                     "chunk_cells": 32768}
+    del T, P, Y, Yo, To
+    torch.cuda.empty_cache()
+    return out, None
+
+
+WORKLOADS = {"fp8_bimodal_2p24": wl_fp8_bimodal, "block_2p27": wl_block, "train_b65536": wl_train,
+             "source_2p20": wl_source, "odenet_2p20": wl_odenet}
 
 
 def _counter_means(path, name_part):

@@ -15,8 +15,13 @@ using namespace chemdnn;
 
 struct chem_dnn {
   int S, L, D, H[3], prec;
-  int widths[5];
+  int widths[9];
   NetLayout lay;
+  // layer-by-layer path (networks the fused kernel does not cover)
+  int layered;
+  int lR[8], lNQ[8];   // per layer: output row-blocks, input k-steps
+  uint8_t *act[2];     // activation fragment buffers of one chunk
+  float *obuf;         // FP32 network output of one chunk [32][chunk]
   int dev, n_cu;
   uint8_t *ws;
   size_t ws_bytes;
@@ -24,8 +29,8 @@ struct chem_dnn {
   float *fc;
   double *dc;
   uint32_t *amax_bits;
-  float *bias[4];
-  void *wpack[4];
+  float *bias[8];
+  void *wpack[8];
   TrainScratch tr;
   int64_t max_batch;
   int thermo;
@@ -65,8 +70,22 @@ int32_t hip_status(hipError_t e) { return e == hipSuccess ? CHEM_DNN_OK : CHEM_D
 
 // Offsets of every sub-buffer inside the workspace.
 struct WsPlan {
-  size_t fc, dc, amax, gtab, bias[4], w[4], train, total;
+  size_t fc, dc, amax, gtab, bias[8], w[8], act[2], obuf, train, total;
 };
+
+// Layer-by-layer path: cells per chunk (activation buffers are sized for it).
+constexpr int64_t kChunk = 32768;
+
+// The layer-by-layer path covers FP32/BF16/FP16 networks with hidden widths
+// that are multiples of 256 (its 256-row tiles), up to 4096.
+bool layered_shape_ok(const chem_dnn_desc *d) {
+  if (d->precision == CHEM_DNN_FP8E4M3 || d->n_layers < 2) return false;
+  for (int l = 1; l < d->n_layers; ++l)
+    if (d->widths[l] % 256 || d->widths[l] > 4096) return false;
+  return true;
+}
+int ks_of(int prec) { return prec == CHEM_DNN_FP32 ? 16 : 32; }
+int eb_of(int prec) { return prec == CHEM_DNN_FP32 ? 4 : 2; }
 
 int32_t check_desc(const chem_dnn_desc *d) {
   if (!d) return CHEM_DNN_EINVAL;
@@ -89,30 +108,57 @@ int32_t check_desc(const chem_dnn_desc *d) {
   if (d->molar_mass)
     for (int s = 0; s < S; ++s)
       if (!(d->molar_mass[s] > 0.0) || !isfinite(d->molar_mass[s])) return CHEM_DNN_EINVAL;
-  if (L != 4) return CHEM_DNN_EUNSUPPORTED;
   return CHEM_DNN_OK;
 }
 
 int32_t plan(const chem_dnn_desc *d, NetLayout *lay, WsPlan *p) {
   int32_t st = check_desc(d);
   if (st) return st;
-  if (!find_layout(d->precision, d->widths[1], d->widths[2], d->widths[3], lay))
-    return CHEM_DNN_EUNSUPPORTED;
+  *lay = NetLayout{};
+  const bool fused = d->n_layers == 4 &&
+                     find_layout(d->precision, d->widths[1], d->widths[2], d->widths[3], lay);
+  if (!fused) {
+    if (!layered_shape_ok(d)) return CHEM_DNN_EUNSUPPORTED;
+    if (d->max_batch > 0) return CHEM_DNN_EUNSUPPORTED;   // training: fused shapes only
+    if (d->gelu_form != CHEM_DNN_GELU_TANH) return CHEM_DNN_EUNSUPPORTED;
+  }
   size_t off = 0;
   p->fc = off; off = align_up(off + FConst::N * sizeof(float));
   p->gtab = off; off = align_up(off + GTAB_N * 4 * sizeof(float));
   p->dc = off; off = align_up(off + DConst::N * sizeof(double));
   p->amax = off; off = align_up(off + 8 * sizeof(uint32_t));
-  for (int l = 0; l < 4; ++l) {
-    p->bias[l] = off;
-    off = align_up(off + (size_t)lay->R[l] * 16 * sizeof(float));
-  }
-  for (int l = 0; l < 4; ++l) {
-    p->w[l] = off;
-    off = align_up(off + (size_t)lay->R[l] * 16 * lay->NQ[l] * lay->KS * lay->EB);
+  const int L = d->n_layers;
+  if (fused) {
+    for (int l = 0; l < 4; ++l) {
+      p->bias[l] = off;
+      off = align_up(off + (size_t)lay->R[l] * 16 * sizeof(float));
+    }
+    for (int l = 0; l < 4; ++l) {
+      p->w[l] = off;
+      off = align_up(off + (size_t)lay->R[l] * 16 * lay->NQ[l] * lay->KS * lay->EB);
+    }
+    p->act[0] = p->act[1] = p->obuf = 0;
+  } else {
+    const int ks = ks_of(d->precision), eb = eb_of(d->precision);
+    int kmax = 32;
+    for (int l = 0; l < L; ++l) {
+      const int R = l == L - 1 ? 2 : d->widths[l + 1] / 16;   // output layer: 32 rows
+      const int K = l == 0 ? 32 : d->widths[l];
+      kmax = K > kmax ? K : kmax;
+      p->bias[l] = off;
+      off = align_up(off + (size_t)R * 16 * sizeof(float));
+      p->w[l] = off;
+      off = align_up(off + (size_t)R * 16 * (K / ks) * ks * eb);
+    }
+    for (int b = 0; b < 2; ++b) {
+      p->act[b] = off;
+      off = align_up(off + (size_t)kmax * kChunk * eb);
+    }
+    p->obuf = off;
+    off = align_up(off + (size_t)32 * kChunk * sizeof(float));
   }
   p->train = off;
-  off += train_scratch_bytes(d->widths, d->max_batch);
+  off += fused ? train_scratch_bytes(d->widths, d->max_batch) : 0;
   p->total = align_up(off);
   return CHEM_DNN_OK;
 }
@@ -154,6 +200,18 @@ int32_t pack_params(chem_dnn *h, const float *params, hipStream_t s) {
                              (int64_t)h->widths[l] * h->widths[l + 1], h->amax_bits + l, s);
   if (e == hipSuccess) e = launch_pow2_scales(h->amax_bits, h->fc, 4, fp8 ? 1 : 0, s);
   static const int fmt_of[4] = {0, 1, 2, 3};
+  if (h->layered) {
+    // output rows unshifted; the w_scale operand is read for FP8 only
+    for (int l = 0; l < h->L && e == hipSuccess; ++l) {
+      const int N = h->widths[l + 1], K = h->widths[l];
+      e = launch_pack(params + param_offset(h->widths, l, false), N, K, 0, h->lR[l], h->lNQ[l],
+                      ks_of(h->prec), fmt_of[h->prec], h->fc + FConst::WSCALE, h->wpack[l], s);
+      if (e == hipSuccess)
+        e = launch_pad_bias(params + param_offset(h->widths, l, true), N, 0, h->lR[l] * 16,
+                            h->bias[l], s);
+    }
+    return hip_status(e);
+  }
   for (int l = 0; l < 4 && e == hipSuccess; ++l) {
     const int N = h->widths[l + 1], K = h->widths[l];
     const int rowshift = (l == 3) ? 2 : 0;
@@ -182,6 +240,39 @@ StepArgs step_args(chem_dnn *h, int64_t n, int64_t ld, const double *T, const do
   a.S = h->S;
   a.thermo = h->thermo;
   return a;
+}
+
+// The layer-by-layer path over chunks of kChunk cells: preprocess, one
+// launch per layer, post-processing.
+int32_t run_layered(chem_dnn *h, int64_t n, int64_t ld, const double *T, const double *P,
+                    const double *Y, double *Y_out, double *T_out, double *omega, double inv_dt,
+                    uint32_t *n_bad, hipStream_t s) {
+  const int fmt = h->prec;   // 0 FP32, 1 BF16, 2 FP16
+  // the chunk buffers lie inside the workspace
+  const uint8_t *end = h->ws + h->ws_bytes;
+  if (h->act[0] < h->ws || h->act[1] < h->ws || (const uint8_t *)h->obuf < h->ws ||
+      (const uint8_t *)(h->obuf + 32 * kChunk) > end)
+    return CHEM_DNN_EWORKSPACE;
+  hipError_t e = hipSuccess;
+  for (int64_t n0 = 0; n0 < n && e == hipSuccess; n0 += kChunk) {
+    const int nc = (int)(n - n0 < kChunk ? n - n0 : kChunk);
+    const int ncb = (nc + 255) / 256 * 16;     // whole 256-cell tiles
+    PrepArgs pa{T, P, Y, ld, n0, nc, ncb, h->act[0], h->fc, h->dc, h->S};
+    e = launch_prep(fmt, pa, s);
+    int cur = 0;
+    for (int l = 0; l < h->L && e == hipSuccess; ++l) {
+      LayerArgs la{h->wpack[l] ? (const uint8_t *)h->wpack[l] : nullptr, h->bias[l], h->act[cur],
+                   h->act[cur ^ 1], h->obuf, h->lR[l], h->lNQ[l], ncb, 16 * ncb};
+      e = launch_layer(fmt, la, l < h->L - 1, s);
+      cur ^= 1;
+    }
+    if (e == hipSuccess) {
+      PostArgs po{T, P, Y, Y_out, T_out, omega, n_bad, ld, n0, nc, 16 * ncb, h->obuf, h->fc,
+                  h->dc, inv_dt, h->S, h->thermo};
+      e = launch_post(po, s);
+    }
+  }
+  return hip_status(e);
 }
 
 int grid_for(const chem_dnn *h, int64_t ntiles) {
@@ -231,7 +322,8 @@ int32_t chem_dnn_init(const chem_dnn_desc *d, const float *params, void *workspa
   int dev = 0, n_cu = 0;
   st = current_device(&dev, &n_cu);
   if (st) return st;
-  if (lay.prepare() != hipSuccess) return CHEM_DNN_EHIP;
+  const bool layered = lay.prepare == nullptr;
+  if ((layered ? layered_prepare() : lay.prepare()) != hipSuccess) return CHEM_DNN_EHIP;
   if (d->max_batch > 0 && train_prepare() != hipSuccess) return CHEM_DNN_EHIP;
 
   chem_dnn *h = new (std::nothrow) chem_dnn();
@@ -239,19 +331,33 @@ int32_t chem_dnn_init(const chem_dnn_desc *d, const float *params, void *workspa
   h->S = d->n_species;
   h->L = d->n_layers;
   h->D = d->widths[0];
-  for (int l = 0; l < 5; ++l) h->widths[l] = d->widths[l];
+  for (int l = 0; l <= h->L; ++l) h->widths[l] = d->widths[l];
   for (int l = 0; l < 3; ++l) h->H[l] = d->widths[l + 1];
+  h->layered = layered ? 1 : 0;
+  if (layered) {
+    const int ks = ks_of(d->precision);
+    for (int l = 0; l < h->L; ++l) {
+      h->lR[l] = l == h->L - 1 ? 2 : d->widths[l + 1] / 16;
+      h->lNQ[l] = (l == 0 ? 32 : d->widths[l]) / ks;
+    }
+  }
   h->prec = d->precision;
   h->lay = lay;
   h->dev = dev;
   h->n_cu = n_cu;
   h->ws = (uint8_t *)workspace;
   h->ws_bytes = workspace_bytes;
+  if (layered) {
+    // (workspace pointers: only once h->ws is set)
+    h->act[0] = h->ws + p.act[0];
+    h->act[1] = h->ws + p.act[1];
+    h->obuf = (float *)(h->ws + p.obuf);
+  }
   h->fc = (float *)(h->ws + p.fc);
   h->gtab = (float *)(h->ws + p.gtab);
   h->dc = (double *)(h->ws + p.dc);
   h->amax_bits = (uint32_t *)(h->ws + p.amax);
-  for (int l = 0; l < 4; ++l) {
+  for (int l = 0; l < (layered ? h->L : 4); ++l) {
     h->bias[l] = (float *)(h->ws + p.bias[l]);
     h->wpack[l] = h->ws + p.w[l];
   }
@@ -331,6 +437,8 @@ int32_t chem_dnn_step(chem_dnn *h, int64_t n, int64_t ld, const double *T, const
   if (n == 0) return CHEM_DNN_OK;
   if (!T || !P || !Y || !Y_out) return CHEM_DNN_EINVAL;
   if (T_out && !h->thermo) return CHEM_DNN_EINVAL;
+  if (h->layered)
+    return run_layered(h, n, ld, T, P, Y, Y_out, T_out, nullptr, 0.0, n_bad, (hipStream_t)stream);
   StepArgs a = step_args(h, n, ld, T, P, Y, Y_out, T_out, n_bad);
   auto launch = h->gelu_form == CHEM_DNN_GELU_TABLE ? h->lay.step_tab : h->lay.step;
   return hip_status(launch(a, grid_for(h, a.ntiles), (hipStream_t)stream));
@@ -346,6 +454,9 @@ int32_t chem_dnn_step_source(chem_dnn *h, int64_t n, int64_t ld, const double *T
   if (T_out && !h->thermo) return CHEM_DNN_EINVAL;
   const void *o = omega;
   if (o == T || o == P || o == Y || o == Y_out || o == T_out) return CHEM_DNN_EINVAL;
+  if (h->layered)
+    return run_layered(h, n, ld, T, P, Y, Y_out, T_out, omega, 1.0 / dt, n_bad,
+                       (hipStream_t)stream);
   StepArgs a = step_args(h, n, ld, T, P, Y, Y_out, T_out, n_bad);
   a.omega = omega;
   a.inv_dt = 1.0 / dt;
@@ -374,9 +485,9 @@ int32_t chem_dnn_get_scales(chem_dnn *h, float *act_scale, float *w_scale, void 
   hipError_t e = hipMemcpyAsync(tmp, h->fc, sizeof(tmp), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return CHEM_DNN_EHIP;
-  for (int l = 0; l < h->L; ++l) {
-    act_scale[l] = tmp[FConst::ASCALE + l];
-    w_scale[l] = tmp[FConst::WSCALE + l];
+  for (int l = 0; l < h->L; ++l) {       // (layers past the fourth: never scaled)
+    act_scale[l] = l < 4 ? tmp[FConst::ASCALE + l] : 1.0f;
+    w_scale[l] = l < 4 ? tmp[FConst::WSCALE + l] : 1.0f;
   }
   return CHEM_DNN_OK;
 }
@@ -384,6 +495,7 @@ int32_t chem_dnn_get_scales(chem_dnn *h, float *act_scale, float *w_scale, void 
 int32_t chem_dnn_mlp_forward(chem_dnn *h, int64_t B, int64_t ld, const float *x,
                              const float *params, float *out, float *saved, void *stream) {
   if (!h || B < 0 || ld < B) return CHEM_DNN_EINVAL;
+  if (h->layered) return CHEM_DNN_EUNSUPPORTED;
   if (B == 0) return CHEM_DNN_OK;
   if (!x || !params || !out) return CHEM_DNN_EINVAL;
   if (!saved && B > h->max_batch) return CHEM_DNN_EINVAL;
@@ -395,6 +507,7 @@ int32_t chem_dnn_mlp_backward(chem_dnn *h, int64_t B, int64_t ld, const float *x
                               const float *params, const float *saved, const float *grad_out,
                               float *grad_params, float *grad_x, void *stream) {
   if (!h || B < 0 || ld < B) return CHEM_DNN_EINVAL;
+  if (h->layered) return CHEM_DNN_EUNSUPPORTED;
   if (!params || !grad_params) return CHEM_DNN_EINVAL;
   if (B > 0 && (!x || !grad_out)) return CHEM_DNN_EINVAL;
   if (B > h->max_batch) return CHEM_DNN_EINVAL;
@@ -406,6 +519,7 @@ int32_t chem_dnn_train_step(chem_dnn *h, int64_t B, int64_t ld, const double *T,
                             const double *Y, const float *target, float *params, float *grads,
                             float *adam_m, float *adam_v, int64_t step, float lr,
                             int32_t recompute, float *loss, void *stream) {
+  if (h && h->layered) return CHEM_DNN_EUNSUPPORTED;
   if (!h || B < 1 || ld < B || B > h->max_batch || step < 1) return CHEM_DNN_EINVAL;
   if (!T || !P || !Y || !target || !params || !grads || !adam_m || !adam_v || !loss)
     return CHEM_DNN_EINVAL;

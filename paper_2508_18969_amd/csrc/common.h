@@ -78,6 +78,35 @@ __device__ __forceinline__ float ypow(double y, float lam) {
   return (y > 0.0 && ef != 0) ? (ef == 0x7ff ? __builtin_inff() : r) : 0.0f;
 }
 
+// The change Y* - Y of one mass fraction y whose Box-Cox value moves by
+// wv = lam delta (delta = the network output after the output statistics):
+// Y* = (max(0, y^lam + wv))^(1/lam).  For a small step it is taken relative to
+// y, Y* - y = y ((1 + t)^(1/lam) - 1) with t = wv / y^lam, which has no
+// cancellation.  Both forms are evaluated without branches on the hardware
+// log2 / exp2.
+__device__ __forceinline__ double inv_change(double y, float wv, float lam, float inv_lam) {
+  const float b = ypow(y, lam);
+  const float t = wv * __builtin_amdgcn_rcpf(b);
+  const bool small = b > 0.0f && __builtin_fabsf(t) <= 0.5f;
+  const float u = 1.0f + t;
+  // log2(1 + t) = log2(u) t / (u - 1) for the rounded u (exact when u == 1)
+  // (both arms of each choice are computed and pinned, so that the choice is
+  // a select, not a branch)
+  float l1a = t * kLog2e, l1b = __builtin_amdgcn_logf(u) * (t * __builtin_amdgcn_rcpf(u - 1.0f));
+  const float base = b + wv;
+  float lb = __builtin_amdgcn_logf(base);
+  asm volatile("" : "+v"(l1a), "+v"(l1b), "+v"(lb));
+  const float z = (small ? (u == 1.0f ? l1a : l1b) : lb) * inv_lam;
+  const float e = __builtin_amdgcn_exp2f(z);
+  // 2^z - 1 = (e - 1) z / log2(e) for the rounded e = 2^z
+  float ema = z * kLn2, emb = (e - 1.0f) * (z * __builtin_amdgcn_rcpf(__builtin_amdgcn_logf(e)));
+  asm volatile("" : "+v"(ema), "+v"(emb));
+  const float em1 = e == 1.0f ? ema : emb;
+  double dys = y * (double)em1, dyl = (base > 0.0f ? (double)e : 0.0) - y;
+  asm volatile("" : "+v"(dys), "+v"(dyl));
+  return small ? dys : dyl;
+}
+
 // Sums and reductions over the lane quartet {l, l ^ 16, l ^ 32, l ^ 48} (the
 // four lanes of one cell) with the row-swap permutes: swapping odd rows of
 // one copy with even rows of another leaves, per lane, its own row's value

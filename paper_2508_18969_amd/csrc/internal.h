@@ -56,6 +56,42 @@ struct StepArgs {
 constexpr int GTAB_N = 600;
 constexpr float GTAB_LO = -3.0f, GTAB_HI = 3.0f, GTAB_INV_H = 100.0f, GTAB_H = 0.01f;
 
+// Layer-by-layer path (layered.hip): arguments of its three kernels.
+struct LayerArgs {
+  const uint8_t *W;      // packed weights [R][NQ] fragments
+  const float *bias;     // [16 R]
+  const uint8_t *X;      // input B fragments [NQ][NCB]
+  uint8_t *Y;            // hidden layers: output B fragments [16 R / KS][NCB]
+  float *O;              // output layer: FP32 [16 R][ldo]
+  int R, NQ, NCB, ldo;   // row-blocks, input k-steps, cell-blocks of the chunk, O's stride
+};
+struct PrepArgs {
+  const double *T, *P, *Y;
+  int64_t ld, n0;        // field stride; first cell of the chunk
+  int nc, NCB;           // cells of the chunk; cell-blocks written (>= nc / 16)
+  uint8_t *X;            // layer-1 B fragments [32 / KS][NCB]
+  const float *fc;
+  const double *dc;
+  int S;
+};
+struct PostArgs {
+  const double *T, *P, *Y;
+  double *Y_out, *T_out, *omega;
+  uint32_t *n_bad;
+  int64_t ld, n0;
+  int nc, ldo;
+  const float *O;        // network output [S][ldo] of the chunk
+  const float *fc;
+  const double *dc;
+  double inv_dt;
+  int S, thermo;
+};
+// fmt: 0 FP32, 1 BF16, 2 FP16 operands
+hipError_t layered_prepare();
+hipError_t launch_prep(int fmt, const PrepArgs &a, hipStream_t s);
+hipError_t launch_layer(int fmt, const LayerArgs &a, bool hidden, hipStream_t s);
+hipError_t launch_post(const PostArgs &a, hipStream_t s);
+
 // Shape and layout of one compiled network configuration.
 struct NetLayout {
   int KS, FRAG, EB;            // operand format of the hidden layers

@@ -1,0 +1,319 @@
+// Layer-by-layer path of the chemistry update for networks whose weights do
+// not fit the on-chip design of the fused kernel - e.g. the ODENet of the
+// paper's runs, 20-2048-4096-2048-1024-512-17 (Sec. 4, network sizes table;
+// 38.9 MFLOP and 19.4M parameters per cell): its 38.9 MB of BF16 weights
+// exceed the 4 MB L2 of an XCD, so every 64-cell tile of the fused kernel
+// would stream them from the Infinity Cache.  Here each layer is one large
+// matrix product over a chunk of cells, with 256 x 256 output tiles whose
+// operands are staged in LDS, so every weight byte fetched serves 256 cells.
+//
+//   prep_kernel    steps 1-2 (power transform, Z-score) -> layer-1 B fragments
+//   layer_kernel   one layer, Zt = W At (+ b, GELU for hidden layers); the
+//                  output goes straight into the next layer's B fragments
+//   post_kernel    steps 4-7 per cell (one thread per cell, FP64 update)
+//
+// Activations live in HBM between layers as "B fragments": for k-step q and
+// cell-block cb (16 cells) a 1 KiB block of 64 lanes x 16 bytes, lane
+// (cell cl, group g) holding input features frag_feature(KS, q, g, j); blocks
+// are ordered [q][cb], so the 16 cell-blocks of a tile are 16 consecutive
+// KiB.  Weights use the fused kernel's packed layout ([row-block][k-step]).
+#include "common.h"
+#include "internal.h"
+
+namespace chemdnn {
+
+namespace {
+
+constexpr int FB = 64 * 16;        // bytes of one fragment (64 lanes x 16 bytes)
+constexpr int STAGES = 3;          // LDS k-step buffers in flight
+
+// Waits until at most N vector-memory operations of this wave are in flight.
+// Direct-to-LDS copies are not tracked by the compiler's own wait insertion;
+// the memory clobber keeps LDS reads from moving above the wait.
+template <int N>
+__device__ __forceinline__ void wait_vmem() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+__device__ __forceinline__ void lds_barrier_all() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// One wave copies the 1 KiB fragment at src (global) to dst (LDS), lane l's
+// 16 bytes to dst + 16 l, without passing through registers.
+__device__ __forceinline__ void dma_frag(const uint8_t *src, uint8_t *dst, int lane) {
+  __builtin_amdgcn_global_load_lds(
+      (const __attribute__((address_space(1))) void *)(src + (uint32_t)(lane * 16)),
+      (__attribute__((address_space(3))) void *)dst, 16, 0, 0);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ layer
+// Workgroup tile: TRB = WRB*WR row-blocks x TCB = WCB*WC cell-blocks; eight
+// waves in a WR x WC grid, each computing WRB x WCB 16x16 output blocks.  Per
+// k-step the tile's TRB weight fragments and TCB activation fragments are
+// copied to an LDS stage (every wave copies every eighth fragment); each wave
+// then reads its WRB + WCB fragments from LDS.  Three stages: the copies of
+// k-step q + 2 are issued once every wave has finished k-step q - 1.
+template <class Op, int WRB, int WR, int WCB, int WC, bool ACT>
+__global__ __launch_bounds__(512, 1) void layer_kernel(LayerArgs a) {
+  static_assert(WR * WC == 8, "eight waves");
+  static_assert(Op::FRAG == 16, "16-byte fragments");
+  using frag_t = typename Op::frag_t;
+  constexpr int TRB = WRB * WR, TCB = WCB * WC, NF = TRB + TCB;
+  constexpr int PERW = NF % 8 == 0 ? NF / 8 : -1;    // copies per wave per k-step, if even
+  extern __shared__ __align__(16) uint8_t smem[];
+  const int lane = threadIdx.x & 63, g = lane >> 4, cl = lane & 15;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wr = w % WR, wc = w / WR;
+  const int nrt = a.R / TRB;
+  const int rt = blockIdx.x % nrt, ct = blockIdx.x / nrt;
+  const int rb0 = rt * TRB, cb0 = ct * TCB;
+  const uint8_t *const Wt = a.W + (size_t)rb0 * a.NQ * FB;
+  const uint8_t *const Xt = a.X + (size_t)cb0 * FB;
+
+  auto issue = [&](int q, int s) {
+    uint8_t *dst = smem + s * NF * FB;
+    for (int f = w; f < NF; f += 8) {
+      const uint8_t *src = f < TRB ? Wt + ((size_t)f * a.NQ + q) * FB
+                                   : Xt + ((size_t)q * a.NCB + (f - TRB)) * FB;
+      dma_frag(src, dst + f * FB, lane);
+    }
+  };
+
+  // accumulators start at the bias (rows 16 rb + 4 g + r)
+  f4 acc[WRB][WCB];
+#pragma unroll
+  for (int i = 0; i < WRB; ++i) {
+    const f4 b = *(const f4 *)(a.bias + 16 * (rb0 + wr * WRB + i) + 4 * g);
+#pragma unroll
+    for (int j = 0; j < WCB; ++j) acc[i][j] = b;
+  }
+
+  issue(0, 0);
+  if (a.NQ > 1) issue(1, 1);
+  for (int q = 0; q < a.NQ; ++q) {
+    // this wave's copies of k-step q have landed (those of q + 1 may not)
+    if constexpr (PERW > 0) {
+      if (q + 1 < a.NQ) wait_vmem<PERW>();
+      else wait_vmem<0>();
+    } else {
+      wait_vmem<0>();
+    }
+    // ... and every wave's; every wave is also done with k-step q - 1
+    lds_barrier_all();
+    if (q + 2 < a.NQ) issue(q + 2, (q + 2) % STAGES);
+    const uint8_t *st = smem + (q % STAGES) * NF * FB + lane * 16;
+    frag_t af[WRB], bf[WCB];
+#pragma unroll
+    for (int i = 0; i < WRB; ++i) af[i] = *(const frag_t *)(st + (wr * WRB + i) * FB);
+#pragma unroll
+    for (int j = 0; j < WCB; ++j) bf[j] = *(const frag_t *)(st + (TRB + wc * WCB + j) * FB);
+#pragma unroll
+    for (int i = 0; i < WRB; ++i)
+#pragma unroll
+      for (int j = 0; j < WCB; ++j) acc[i][j] = Op::mma(af[i], bf[j], acc[i][j]);
+  }
+
+  if constexpr (ACT) {
+    // GELU, then the next layer's B fragments: output row 16 rb + 4 g + r is
+    // input feature of k-step rb / RPQ, slot 4 (rb % RPQ) + r
+    constexpr int RPQ = Op::KS / 16;
+    static_assert(WRB % RPQ == 0, "row-blocks of a k-step in one wave");
+#pragma unroll
+    for (int i = 0; i < WRB; i += RPQ) {
+      const int rb = rb0 + wr * WRB + i;
+#pragma unroll
+      for (int j = 0; j < WCB; ++j) {
+        const int cb = cb0 + wc * WCB + j;
+        __attribute__((aligned(16))) uint8_t buf[16];
+#pragma unroll
+        for (int k = 0; k < RPQ; ++k) {
+          f4 y;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) y[r] = gelu(acc[i + k][j][r]);
+          Op::store4(buf + 4 * k * Op::EB, y);
+        }
+        *(i4 *)(a.Y + ((size_t)(rb / RPQ) * a.NCB + cb) * FB + lane * 16) = *(const i4 *)buf;
+      }
+    }
+  } else {
+    // output layer: FP32 [row][cell]
+#pragma unroll
+    for (int i = 0; i < WRB; ++i)
+#pragma unroll
+      for (int j = 0; j < WCB; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          a.O[(size_t)(16 * (rb0 + wr * WRB + i) + 4 * g + r) * a.ldo + 16 * (cb0 + wc * WCB + j) + cl] =
+              acc[i][j][r];
+  }
+}
+
+// ------------------------------------------------------------------ prep
+// Thread per cell c of the chunk (cells past the chunk give zero features):
+// z_f of steps 1-2 for f < 32, written into the layer-1 B fragments.
+template <class Op>
+__global__ __launch_bounds__(256) void prep_kernel(PrepArgs a) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= 16 * a.NCB) return;
+  const int64_t i = a.n0 + c;
+  const bool valid = c < a.nc;
+  const int64_t ii = valid ? i : 0;
+  const float lam = a.fc[FConst::LAM];
+  float z[32];
+#pragma unroll
+  for (int f = 0; f < 32; ++f) {
+    float v = 0.0f;
+    if (valid) {
+      if (f == 0) {
+        v = (float)((a.T[ii] - a.dc[DConst::T_MU]) * a.dc[DConst::T_IS]);
+      } else if (f == 1) {
+        v = (float)((a.P[ii] - a.dc[DConst::P_MU]) * a.dc[DConst::P_IS]);
+      } else if (f - 2 < a.S) {
+        v = __builtin_fmaf(ypow(a.Y[(int64_t)(f - 2) * a.ld + ii], lam), a.fc[FConst::ZA + f],
+                           a.fc[FConst::ZC + f]);
+      }
+    }
+    z[f] = v;
+  }
+  const int cb = c >> 4, cl = c & 15;
+  constexpr int NE = 16 / Op::EB;                          // slots per lane
+#pragma unroll
+  for (int q = 0; q < 32 / Op::KS; ++q)
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      __attribute__((aligned(16))) uint8_t buf[16];
+#pragma unroll
+      for (int j0 = 0; j0 < NE; j0 += 4) {
+        f4 y;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) y[r] = z[frag_feature(Op::KS, q, g, j0 + r)];
+        Op::store4(buf + j0 * Op::EB, y);
+      }
+      *(i4 *)(a.X + ((size_t)q * a.NCB + cb) * FB + (g * 16 + cl) * 16) = *(const i4 *)buf;
+    }
+}
+
+// ------------------------------------------------------------------ post
+// Thread per cell: steps 4-7 from the FP32 network output O[s][cell].
+__global__ __launch_bounds__(256) void post_kernel(PostArgs a) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= a.nc) return;
+  const int64_t i = a.n0 + c;
+  const float lam = a.fc[FConst::LAM], inv_lam = a.fc[FConst::INV_LAM];
+  const double T = a.T[i], P = a.P[i], t_ref = a.dc[DConst::T_REF];
+  bool bad = !__builtin_isfinite(T) || !__builtin_isfinite(P);
+  double ssum = 0.0, h0 = 0.0, ry = 0.0;
+  for (int s = 0; s < a.S; ++s) {
+    const int rho = s + 2;
+    const double y = a.Y[(int64_t)s * a.ld + i];
+    bad |= !__builtin_isfinite(y);
+    const float o = a.O[(size_t)s * a.ldo + c];
+    double yh = y + inv_change(y, __builtin_fmaf(o, a.fc[FConst::PA + rho], a.fc[FConst::PB + rho]),
+                               lam, inv_lam);
+    yh = yh > 0.0 ? yh : 0.0;
+    ssum += yh;
+    h0 += y * (a.dc[DConst::HF + rho] + a.dc[DConst::CP + rho] * (T - t_ref));
+    ry += y * a.dc[DConst::WINV + rho];
+  }
+  const double rsum = 1.0 / ssum;
+  double hn = 0.0, cn = 0.0;
+  bool nonfin = false;
+  for (int s = 0; s < a.S; ++s) {
+    const double y = a.Y[(int64_t)s * a.ld + i];
+    const float o = a.O[(size_t)s * a.ldo + c];
+    // recomputed instead of kept: the species loop stays in registers
+    double yh = y + inv_change(y, __builtin_fmaf(o, a.fc[FConst::PA + s + 2], a.fc[FConst::PB + s + 2]),
+                               lam, inv_lam);
+    yh = yh > 0.0 ? yh : 0.0;
+    const double yn = yh * rsum;
+    nonfin |= !__builtin_isfinite(yn);
+    hn += yn * a.dc[DConst::HF + s + 2];
+    cn += yn * a.dc[DConst::CP + s + 2];
+  }
+  const double Tn = a.thermo ? t_ref + (h0 - hn) / cn : T;
+  const bool okc = !bad && !nonfin && ssum > 0.0 && __builtin_isfinite(ssum) && __builtin_isfinite(Tn);
+  const double rho_dt = a.omega && okc ? P / (kRGas * T * ry) * a.inv_dt : 0.0;
+  for (int s = 0; s < a.S; ++s) {
+    const double y = a.Y[(int64_t)s * a.ld + i];
+    double yn = y;
+    if (okc) {
+      const float o = a.O[(size_t)s * a.ldo + c];
+      double yh = y + inv_change(y, __builtin_fmaf(o, a.fc[FConst::PA + s + 2], a.fc[FConst::PB + s + 2]),
+                                 lam, inv_lam);
+      yn = (yh > 0.0 ? yh : 0.0) * rsum;
+    }
+    a.Y_out[(int64_t)s * a.ld + i] = yn;
+    if (a.omega) a.omega[(int64_t)s * a.ld + i] = okc ? rho_dt * (yn - y) : 0.0;
+  }
+  if (a.T_out) a.T_out[i] = okc ? Tn : T;
+  if (!okc && a.n_bad) atomicAdd(a.n_bad, 1u);
+}
+
+// ------------------------------------------------------------------ launchers
+namespace {
+
+template <class K>
+hipError_t set_lds(K kern, int bytes) {
+  return hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+constexpr int LDS_HIDDEN = STAGES * (16 + 16) * FB;
+
+template <class Op>
+hipError_t launch_layer_op(const LayerArgs &a, bool hidden, hipStream_t s) {
+  if (hidden) {
+    // 256 x 256 tiles: 16 row-blocks (4 per wave) x 16 cell-blocks (8 per wave)
+    auto k = layer_kernel<Op, 4, 4, 8, 2, true>;
+    const int grid = (a.R / 16) * (a.NCB / 16);
+    constexpr int LDS = LDS_HIDDEN;
+    hipLaunchKernelGGL(k, dim3(grid), dim3(512), LDS, s, a);
+  } else {
+    // output layer, 32 rows: 2 row-blocks x 16 cell-blocks (2 per wave)
+    constexpr int NF = 2 + 16, LDS = STAGES * NF * FB;
+    auto k = layer_kernel<Op, 2, 1, 2, 8, false>;
+    const int grid = (a.R / 2) * (a.NCB / 16);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(512), LDS, s, a);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+// The hidden-layer kernels use more than the default 64 KiB of LDS.
+hipError_t layered_prepare() {
+  hipError_t e = set_lds(layer_kernel<OpF32, 4, 4, 8, 2, true>, LDS_HIDDEN);
+  if (e == hipSuccess) e = set_lds(layer_kernel<OpBF16, 4, 4, 8, 2, true>, LDS_HIDDEN);
+  if (e == hipSuccess) e = set_lds(layer_kernel<OpF16, 4, 4, 8, 2, true>, LDS_HIDDEN);
+  return e;
+}
+
+hipError_t launch_layer(int fmt, const LayerArgs &a, bool hidden, hipStream_t s) {
+  switch (fmt) {
+    case 0: return launch_layer_op<OpF32>(a, hidden, s);
+    case 1: return launch_layer_op<OpBF16>(a, hidden, s);
+    case 2: return launch_layer_op<OpF16>(a, hidden, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_prep(int fmt, const PrepArgs &a, hipStream_t s) {
+  const int blocks = (16 * a.NCB + 255) / 256;
+  switch (fmt) {
+    case 0: hipLaunchKernelGGL(prep_kernel<OpF32>, dim3(blocks), dim3(256), 0, s, a); break;
+    case 1: hipLaunchKernelGGL(prep_kernel<OpBF16>, dim3(blocks), dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL(prep_kernel<OpF16>, dim3(blocks), dim3(256), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_post(const PostArgs &a, hipStream_t s) {
+  if (a.nc <= 0) return hipSuccess;
+  hipLaunchKernelGGL(post_kernel, dim3((a.nc + 255) / 256), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace chemdnn

@@ -721,32 +721,8 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
             const double y = sp ? Yc[j] : 0.0;
             Y[j] = y;
             bad |= !__builtin_isfinite(y);
-            const float b = ypow(y, lam);
-            const float wv = __builtin_fmaf(o[h][r], fcl[FConst::PA + rho], fcl[FConst::PB + rho]);
-            // Inverse Box-Cox, Y* = (b + wv)^(1/lam) clamped at 0.  For a small
-            // step it is taken relative to Y, Y* - Y = Y ((1 + t)^(1/lam) - 1)
-            // with t = wv / b, which has no cancellation.  Both forms are
-            // evaluated without branches on the hardware log2 / exp2.
-            const float t = wv * __builtin_amdgcn_rcpf(b);
-            const bool small = b > 0.0f && __builtin_fabsf(t) <= 0.5f;
-            const float u = 1.0f + t;
-            // log2(1 + t) = log2(u) t / (u - 1) for the rounded u (exact when u == 1)
-            // (both arms of each choice are computed and pinned, so that the
-            // choice is a select, not a branch)
-            float l1a = t * kLog2e, l1b = __builtin_amdgcn_logf(u) * (t * __builtin_amdgcn_rcpf(u - 1.0f));
-            const float base = b + wv;
-            float lb = __builtin_amdgcn_logf(base);
-            asm volatile("" : "+v"(l1a), "+v"(l1b), "+v"(lb));
-            const float z = (small ? (u == 1.0f ? l1a : l1b) : lb) * inv_lam;
-            const float e = __builtin_amdgcn_exp2f(z);
-            // 2^z - 1 = (e - 1) z / log2(e) for the rounded e = 2^z
-            float ema = z * kLn2, emb = (e - 1.0f) * (z * __builtin_amdgcn_rcpf(__builtin_amdgcn_logf(e)));
-            asm volatile("" : "+v"(ema), "+v"(emb));
-            const float em1 = e == 1.0f ? ema : emb;
-            double dys = y * (double)em1, dyl = (base > 0.0f ? (double)e : 0.0) - y;
-            asm volatile("" : "+v"(dys), "+v"(dyl));
-            const double dy = small ? dys : dyl;
-            double yh = y + dy;
+            double yh = y + inv_change(y, __builtin_fmaf(o[h][r], fcl[FConst::PA + rho], fcl[FConst::PB + rho]),
+                                       lam, inv_lam);
             yh = sp && yh > 0.0 ? yh : 0.0;
             Yh[j] = yh;
             ssum += yh;

@@ -39,6 +39,9 @@ STREAMS = ("weights", "inputs", "calibration", "mechanism", "subsample", "extra"
 # S outputs, three GELU hidden layers.
 NET_SMALL = (19, 400, 200, 100, 17)     # 17 species
 NET_LARGE = (31, 1600, 800, 400, 29)    # 29 species
+# the ODENet size of the paper's runs (20-2048-4096-2048-1024-512-17) with
+# S + 2 = 19 inputs for 17 species
+NET_ODENET = (19, 2048, 4096, 2048, 1024, 512, 17)
 BOXCOX_LAMBDA = 0.1
 
 T_UNIFORM = (300.0, 3000.0)        # K
@@ -47,7 +50,8 @@ DIRICHLET_ALPHA = 0.5
 
 
 def streams(config: int) -> dict:
-    """Named independent generators for workload ``config`` (1..5)."""
+    """Named independent generators for workload ``config`` (1..5; 6 is the
+    paper-size ODENet over the states of workload 1)."""
     ss = np.random.SeedSequence(SEED_BASE + 1000 * int(config))
     kids = ss.spawn(len(STREAMS))
     return {name: np.random.Generator(np.random.PCG64(k)) for name, k in zip(STREAMS, kids)}
@@ -272,7 +276,7 @@ def make_net(config: int, widths=None, bias_scale: float = 0.0) -> Net:
     raw output is taken as the normalised Box-Cox increment.
     """
     if widths is None:
-        widths = NET_SMALL if config in (1, 4) else NET_LARGE
+        widths = NET_SMALL if config in (1, 4) else NET_ODENET if config == 6 else NET_LARGE
     rng = streams(config)["weights"]
     W, b = xavier_weights(rng, widths, bias_scale)
     S = widths[-1]
@@ -283,7 +287,7 @@ def make_net(config: int, widths=None, bias_scale: float = 0.0) -> Net:
 def make_state(config: int, n: int, stream: str = "inputs", S: int | None = None) -> State:
     """Seeded input states of a workload (n cells)."""
     if S is None:
-        S = 17 if config in (1, 4) else 29
+        S = 17 if config in (1, 4, 6) else 29
     rng = streams(config)[stream]
     if config == 3:
         return draw_bimodal_state(rng, S, n)
