@@ -25,7 +25,7 @@ namespace chemdnn {
 namespace {
 
 constexpr int FB = 64 * 16;        // bytes of one fragment (64 lanes x 16 bytes)
-constexpr int STAGES = 3;          // LDS k-step buffers in flight
+constexpr int STAGES = 4;          // LDS k-step buffers in flight
 
 // Waits until at most N vector-memory operations of this wave are in flight.
 // Direct-to-LDS copies are not tracked by the compiler's own wait insertion;
@@ -54,15 +54,17 @@ __device__ __forceinline__ void dma_frag(const uint8_t *src, uint8_t *dst, int l
 // waves in a WR x WC grid, each computing WRB x WCB 16x16 output blocks.  Per
 // k-step the tile's TRB weight fragments and TCB activation fragments are
 // copied to an LDS stage (every wave copies every eighth fragment); each wave
-// then reads its WRB + WCB fragments from LDS.  Three stages: the copies of
-// k-step q + 2 are issued once every wave has finished k-step q - 1.
+// then reads its WRB + WCB fragments from LDS into registers one k-step ahead,
+// so that the reads of k-step q + 1 overlap the products of k-step q.  Four
+// stages: the copies of k-step q + 3 are issued once every wave has read the
+// fragments of k-step q (and so is done with the stage of q - 1).
 template <class Op, int WRB, int WR, int WCB, int WC, bool ACT>
-__global__ __launch_bounds__(512, 1) void layer_kernel(LayerArgs a) {
-  static_assert(WR * WC == 8, "eight waves");
+__global__ __launch_bounds__(WR * WC * 64, 1) void layer_kernel(LayerArgs a) {
+  constexpr int NW = WR * WC;                         // waves
   static_assert(Op::FRAG == 16, "16-byte fragments");
   using frag_t = typename Op::frag_t;
   constexpr int TRB = WRB * WR, TCB = WCB * WC, NF = TRB + TCB;
-  constexpr int PERW = NF % 8 == 0 ? NF / 8 : -1;    // copies per wave per k-step, if even
+  constexpr int PERW = NF % NW == 0 ? NF / NW : -1;  // copies per wave per k-step, if even
   extern __shared__ __align__(16) uint8_t smem[];
   const int lane = threadIdx.x & 63, g = lane >> 4, cl = lane & 15;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -73,13 +75,31 @@ __global__ __launch_bounds__(512, 1) void layer_kernel(LayerArgs a) {
   const uint8_t *const Wt = a.W + (size_t)rb0 * a.NQ * FB;
   const uint8_t *const Xt = a.X + (size_t)cb0 * FB;
 
+  // this wave's copies: fragments f = w + NW k of the NF of a k-step
   auto issue = [&](int q, int s) {
     uint8_t *dst = smem + s * NF * FB;
-    for (int f = w; f < NF; f += 8) {
-      const uint8_t *src = f < TRB ? Wt + ((size_t)f * a.NQ + q) * FB
-                                   : Xt + ((size_t)q * a.NCB + (f - TRB)) * FB;
-      dma_frag(src, dst + f * FB, lane);
+    if constexpr (TRB % NW == 0 && TCB % NW == 0) {
+#pragma unroll
+      for (int k = 0; k < NF / NW; ++k) {
+        const int f = w + NW * k;
+        const uint8_t *src = k < TRB / NW ? Wt + ((size_t)f * a.NQ + q) * FB
+                                          : Xt + ((size_t)q * a.NCB + (f - TRB)) * FB;
+        dma_frag(src, dst + f * FB, lane);
+      }
+    } else {
+      for (int f = w; f < NF; f += NW) {
+        const uint8_t *src = f < TRB ? Wt + ((size_t)f * a.NQ + q) * FB
+                                     : Xt + ((size_t)q * a.NCB + (f - TRB)) * FB;
+        dma_frag(src, dst + f * FB, lane);
+      }
     }
+  };
+  auto read = [&](int q, frag_t (&af)[WRB], frag_t (&bf)[WCB]) {
+    const uint8_t *st = smem + (q % STAGES) * NF * FB + lane * 16;
+#pragma unroll
+    for (int i = 0; i < WRB; ++i) af[i] = *(const frag_t *)(st + (wr * WRB + i) * FB);
+#pragma unroll
+    for (int j = 0; j < WCB; ++j) bf[j] = *(const frag_t *)(st + (TRB + wc * WCB + j) * FB);
   };
 
   // accumulators start at the bias (rows 16 rb + 4 g + r)
@@ -91,29 +111,43 @@ __global__ __launch_bounds__(512, 1) void layer_kernel(LayerArgs a) {
     for (int j = 0; j < WCB; ++j) acc[i][j] = b;
   }
 
-  issue(0, 0);
-  if (a.NQ > 1) issue(1, 1);
-  for (int q = 0; q < a.NQ; ++q) {
-    // this wave's copies of k-step q have landed (those of q + 1 may not)
-    if constexpr (PERW > 0) {
-      if (q + 1 < a.NQ) wait_vmem<PERW>();
-      else wait_vmem<0>();
-    } else {
-      wait_vmem<0>();
+  // k-steps 0 .. STAGES - 2 in flight; k-step 0 in registers
+  for (int q = 0; q < STAGES - 1 && q < a.NQ; ++q) issue(q, q);
+  if constexpr (PERW > 0) {
+    if (a.NQ > 2) wait_vmem<PERW * (STAGES - 2)>();
+    else wait_vmem<0>();
+  } else {
+    wait_vmem<0>();
+  }
+  lds_barrier_all();
+  frag_t af[2][WRB], bf[2][WCB];
+  read(0, af[0], bf[0]);
+  for (int q = 0; q < a.NQ; q += 2) {
+    // two k-steps per trip, so the register buffers need no dynamic index
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int qq = q + h;
+      if (qq < a.NQ) {
+        if (qq + 1 < a.NQ) {
+          // k-step qq + 1: this wave's copies (those of qq + 2 may be in
+          // flight), then every wave's; every wave has read k-step qq, so the
+          // stage of qq - 1 is free for k-step qq + 3
+          if constexpr (PERW > 0) {
+            if (qq + 2 < a.NQ) wait_vmem<PERW>();
+            else wait_vmem<0>();
+          } else {
+            wait_vmem<0>();
+          }
+          lds_barrier_all();
+          if (qq + STAGES - 1 < a.NQ) issue(qq + STAGES - 1, (qq + STAGES - 1) % STAGES);
+          read(qq + 1, af[h ^ 1], bf[h ^ 1]);
+        }
+#pragma unroll
+        for (int i = 0; i < WRB; ++i)
+#pragma unroll
+          for (int j = 0; j < WCB; ++j) acc[i][j] = Op::mma(af[h][i], bf[h][j], acc[i][j]);
+      }
     }
-    // ... and every wave's; every wave is also done with k-step q - 1
-    lds_barrier_all();
-    if (q + 2 < a.NQ) issue(q + 2, (q + 2) % STAGES);
-    const uint8_t *st = smem + (q % STAGES) * NF * FB + lane * 16;
-    frag_t af[WRB], bf[WCB];
-#pragma unroll
-    for (int i = 0; i < WRB; ++i) af[i] = *(const frag_t *)(st + (wr * WRB + i) * FB);
-#pragma unroll
-    for (int j = 0; j < WCB; ++j) bf[j] = *(const frag_t *)(st + (TRB + wc * WCB + j) * FB);
-#pragma unroll
-    for (int i = 0; i < WRB; ++i)
-#pragma unroll
-      for (int j = 0; j < WCB; ++j) acc[i][j] = Op::mma(af[i], bf[j], acc[i][j]);
   }
 
   if constexpr (ACT) {
@@ -260,19 +294,24 @@ hipError_t set_lds(K kern, int bytes) {
   return hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
+// hidden layers: 256 x 256 tiles (16 row-blocks x 16 cell-blocks) over
+// HWR x HWC waves of HWRB x HWCB blocks each
+constexpr int HWRB = 4, HWR = 4, HWCB = 8, HWC = 2;
+static_assert(HWRB * HWR == 16 && HWCB * HWC == 16, "256 x 256 tiles");
 constexpr int LDS_HIDDEN = STAGES * (16 + 16) * FB;
+constexpr int LDS_OUT = STAGES * (2 + 16) * FB;
+static_assert(LDS_HIDDEN <= 160 * 1024, "LDS budget");
 
 template <class Op>
 hipError_t launch_layer_op(const LayerArgs &a, bool hidden, hipStream_t s) {
   if (hidden) {
-    // 256 x 256 tiles: 16 row-blocks (4 per wave) x 16 cell-blocks (8 per wave)
-    auto k = layer_kernel<Op, 4, 4, 8, 2, true>;
+    auto k = layer_kernel<Op, HWRB, HWR, HWCB, HWC, true>;
     const int grid = (a.R / 16) * (a.NCB / 16);
-    constexpr int LDS = LDS_HIDDEN;
-    hipLaunchKernelGGL(k, dim3(grid), dim3(512), LDS, s, a);
+    constexpr int LDS = LDS_HIDDEN, NT = 64 * HWR * HWC;
+    hipLaunchKernelGGL(k, dim3(grid), dim3(NT), LDS, s, a);
   } else {
     // output layer, 32 rows: 2 row-blocks x 16 cell-blocks (2 per wave)
-    constexpr int NF = 2 + 16, LDS = STAGES * NF * FB;
+    constexpr int LDS = LDS_OUT;
     auto k = layer_kernel<Op, 2, 1, 2, 8, false>;
     const int grid = (a.R / 2) * (a.NCB / 16);
     hipLaunchKernelGGL(k, dim3(grid), dim3(512), LDS, s, a);
@@ -282,11 +321,14 @@ hipError_t launch_layer_op(const LayerArgs &a, bool hidden, hipStream_t s) {
 
 }  // namespace
 
-// The hidden-layer kernels use more than the default 64 KiB of LDS.
+// The layer kernels use more than the default 64 KiB of LDS.
 hipError_t layered_prepare() {
-  hipError_t e = set_lds(layer_kernel<OpF32, 4, 4, 8, 2, true>, LDS_HIDDEN);
-  if (e == hipSuccess) e = set_lds(layer_kernel<OpBF16, 4, 4, 8, 2, true>, LDS_HIDDEN);
-  if (e == hipSuccess) e = set_lds(layer_kernel<OpF16, 4, 4, 8, 2, true>, LDS_HIDDEN);
+  hipError_t e = set_lds(layer_kernel<OpF32, HWRB, HWR, HWCB, HWC, true>, LDS_HIDDEN);
+  if (e == hipSuccess) e = set_lds(layer_kernel<OpBF16, HWRB, HWR, HWCB, HWC, true>, LDS_HIDDEN);
+  if (e == hipSuccess) e = set_lds(layer_kernel<OpF16, HWRB, HWR, HWCB, HWC, true>, LDS_HIDDEN);
+  if (e == hipSuccess) e = set_lds(layer_kernel<OpF32, 2, 1, 2, 8, false>, LDS_OUT);
+  if (e == hipSuccess) e = set_lds(layer_kernel<OpBF16, 2, 1, 2, 8, false>, LDS_OUT);
+  if (e == hipSuccess) e = set_lds(layer_kernel<OpF16, 2, 1, 2, 8, false>, LDS_OUT);
   return e;
 }
 
