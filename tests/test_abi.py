@@ -91,3 +91,27 @@ def test_init_without_device_reports_enodev(L):
     out = C.c_void_p()
     st = L.lib().chem_dnn_init(C.byref(d), C.c_void_p(16), C.c_void_p(addr), n, None, C.byref(out))
     assert st == L.ENODEV and not out.value
+
+
+def test_layered_shapes_workspace_and_limits(L):
+    """Networks outside the fused shapes run layer by layer when their hidden
+    widths are multiples of 256 (FP32/BF16/FP16, tanh GELU, no training): the
+    workspace then also holds two chunk-sized activation buffers."""
+    net = synth.make_net(6)
+    assert net.widths == (19, 2048, 4096, 2048, 1024, 512, 17)
+    d, keep = L.make_desc(net.widths, "bf16", net.in_mean, net.in_std)
+    n = L.workspace_bytes(d)
+    weights = 2 * sum(a * b for a, b in zip((32,) + net.widths[1:-1], net.widths[1:-1] + (32,)))
+    assert n >= weights + 2 * 4096 * 32768 * 2 + 32 * 32768 * 4
+    d32, k32 = L.make_desc(net.widths, "fp32", net.in_mean, net.in_std)
+    assert L.workspace_bytes(d32) > n
+    for kw in (dict(precision="fp8", act_amax=np.ones(6, np.float32)),   # no FP8 there
+               dict(max_batch=1024),                                     # no training there
+               dict(gelu="table"),                                       # tanh form only
+               dict(widths=(19, 2048, 4000, 2048, 1024, 512, 17))):      # not a multiple of 256
+        args = dict(widths=net.widths, precision="bf16", in_mean=net.in_mean, in_std=net.in_std)
+        args.update(kw)
+        d2, k2 = L.make_desc(**args)
+        with pytest.raises(L.ChemDNNError) as e:
+            L.workspace_bytes(d2)
+        assert e.value.status == L.EUNSUPPORTED, kw
