@@ -5,7 +5,7 @@ import pytest
 
 import synth
 from oracle import chem, train
-from tests.helpers import dev_state, make_handle
+from tests.helpers import dev_state, make_handle, rel_err
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -208,3 +208,54 @@ def test_binding_rejects_wrong_layouts():
     # the same data in row layout is accepted
     h.train_step(T, P, Y, tgt_f.contiguous(), p, g, m, v, 1)
     torch.cuda.synchronize()
+
+
+def test_set_params_after_training():
+    """Train a few Adam steps on an FP32 handle, load the trained parameters
+    into separate inference handles with chem_dnn_set_params (FP32 and BF16;
+    FP8 re-derives its weight scales), and compare their updates with the
+    oracle evaluating the trained parameters."""
+    import dataclasses
+    print("case set_params after training", flush=True)
+    B = 2048
+    net = synth.make_net(4)
+    st = synth.make_state(4, B)
+    rng = np.random.default_rng(11)
+    tgt = torch.tensor(0.3 * rng.standard_normal((17, B)), dtype=torch.float32, device="cuda")
+    ht = make_handle(net, "fp32", max_batch=B)
+    T, P, Y = dev_state(st)
+    p = torch.tensor(net.flat_params(), device="cuda")
+    m, v, g = torch.zeros_like(p), torch.zeros_like(p), torch.empty_like(p)
+    for k in range(1, 6):
+        ht.train_step(T, P, Y, tgt, p, g, m, v, k, lr=1e-2)
+    torch.cuda.synchronize()
+    pt = p.cpu().numpy()
+    W, b = train.unflatten(pt, WIDTHS)
+    trained = dataclasses.replace(net, W=[w.astype(np.float32) for w in W],
+                                  b=[x.astype(np.float32) for x in b])
+    assert np.max(np.abs(pt - net.flat_params())) > 1e-3        # the weights did move
+    thermo = synth.make_thermo(4, 17)
+    ref = chem.step(st.T, st.P, st.Y, trained, thermo=thermo)
+    h32 = make_handle(net, "fp32", thermo=thermo)               # packed from the initial weights
+    h32.set_params(p)
+    Y32, T32 = h32.step(T, P, Y)
+    hb = make_handle(net, "bf16", thermo=thermo)
+    hb.set_params(p)
+    Yb, Tb = hb.step(T, P, Y)
+    torch.cuda.synchronize()
+    assert rel_err(Y32.cpu().numpy(), ref["Y_new"]) <= 1e-5
+    assert rel_err(T32.cpu().numpy(), ref["T_new"], floor=1.0) <= 1e-5
+    # BF16 after set_params equals BF16 built from the trained weights
+    hb2 = make_handle(trained, "bf16", thermo=thermo)
+    Yb2, Tb2 = hb2.step(T, P, Y)
+    torch.cuda.synchronize()
+    assert torch.equal(Yb, Yb2) and torch.equal(Tb, Tb2)
+    # FP8: set_params re-derives the weight scales from the new weights
+    amax = chem.layer_input_amax(st.T, st.P, st.Y, trained).astype(np.float32)
+    h8 = make_handle(net, "fp8", thermo=thermo, act_amax=amax)
+    h8.set_params(p)
+    h8b = make_handle(trained, "fp8", thermo=thermo, act_amax=amax)
+    Y8, _ = h8.step(T, P, Y)
+    Y8b, _ = h8b.step(T, P, Y)
+    torch.cuda.synchronize()
+    assert torch.equal(Y8, Y8b)
