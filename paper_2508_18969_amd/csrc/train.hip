@@ -106,6 +106,108 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
       }
 }
 
+// Weight-gradient partial of one K-split, for operands whose reduction index
+// (the batch) is contiguous: C[m][n] = sum_k A[m][k] B'[n][k], B' = GELU(B) if
+// gelu_b.  The workgroup's 64x64 tile is computed by each of its four waves
+// over a quarter of the split (straight from global memory: each lane loads 4
+// consecutive k of one row, and the four 16x16x4 products of a 16-k block take
+// them in turn - the same k permutation on both operands), then the four
+// partial tiles are summed in LDS in wave order.  Requires A and B rows 16-byte
+// aligned (leading dimensions multiples of 4).
+__global__ __launch_bounds__(256) void dw_kernel(GemmArgs g) {
+  __shared__ float red[2][64][65];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g4 = lane >> 4, c16 = lane & 15;
+  const int64_t m0 = (int64_t)blockIdx.y * 64, n0 = (int64_t)blockIdx.x * 64;
+  const int64_t k0 = (int64_t)blockIdx.z * g.kchunk;
+  const int64_t k1 = (k0 + g.kchunk < g.K) ? k0 + g.kchunk : g.K;
+  const int64_t ks = ((g.kchunk + 3) / 4 + 15) / 16 * 16;          // per wave, whole 16-k blocks
+  const int64_t kb0 = k0 + w * ks;
+  const int64_t kb1 = (kb0 + ks < k1) ? kb0 + ks : k1;
+  f4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+  // the rows this lane reads (clamped into range; their values are zeroed)
+  int64_t ra[4], rb[4];
+  bool va[4], vb[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t m = m0 + 16 * i + c16, n = n0 + 16 * i + c16;
+    va[i] = m < g.M;
+    vb[i] = n < g.N;
+    ra[i] = (va[i] ? m : 0) * g.sam;
+    rb[i] = (vb[i] ? n : 0) * g.sbn;
+  }
+  for (int64_t kb = kb0; kb < kb1; kb += 16) {
+    const int64_t k = kb + 4 * g4;
+    f4 a[4], b[4];
+    if (kb + 16 <= kb1) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        a[i] = *(const f4 *)(g.A + ra[i] + k);
+        b[i] = *(const f4 *)(g.B + rb[i] + k);
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          a[i][e] = k + e < kb1 ? g.A[ra[i] + k + e] : 0.0f;
+          b[i][e] = k + e < kb1 ? g.B[rb[i] + k + e] : 0.0f;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (!va[i]) a[i][e] = 0.0f;
+        float v = vb[i] ? b[i][e] : 0.0f;
+        if (g.gelu_b) v = gelu(v);
+        // zero past the batch (gelu(0) = 0 as well)
+        b[i][e] = (k + e < kb1) ? v : 0.0f;
+      }
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][e], b[j][e], acc[i][j], 0, 0, 0);
+  }
+  // the waves' partial tiles, summed in wave order ((w0 + w1) + w2) + w3,
+  // through LDS in two halves
+  auto put = [&](int slot) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) red[slot][16 * i + 4 * g4 + r][16 * j + c16] = acc[i][j][r];
+  };
+  if (w < 2) put(w);
+  __syncthreads();
+  float v[16];
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    const int e = tid + 256 * t, mm = e >> 6, nn = e & 63;
+    v[t] = red[0][mm][nn] + red[1][mm][nn];
+  }
+  __syncthreads();
+  if (w >= 2) put(w - 2);
+  __syncthreads();
+  float *C = g.C + blockIdx.z * g.part_stride;
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    const int e = tid + 256 * t, mm = e >> 6, nn = e & 63;
+    const int64_t m = m0 + mm, n = n0 + nn;
+    float x = v[t];
+    x += red[0][mm][nn];
+    x += red[1][mm][nn];
+    if (m < g.M && n < g.N) C[m * g.scm + n * g.scn] = x;
+  }
+}
+
 // out[i] = sum over z of part[z * stride + i], z in increasing order.
 __global__ void reduce_parts_kernel(const float *part, int64_t stride, int nz, int64_t n,
                                     float *out) {
@@ -267,7 +369,14 @@ hipError_t backward(const int *w, int64_t B, const float *x, int64_t ldx, const 
     g.C = t->part; g.scm = K; g.scn = 1;
     g.M = N; g.N = K; g.K = B; g.kchunk = kchunk;
     g.part_stride = (int64_t)N * K;
-    hipError_t e = gemm(EPI_PART, g, nsplit, s);
+    hipError_t e;
+    if (lddz % 4 == 0 && ldain % 4 == 0 && ((uintptr_t)dZ | (uintptr_t)ain) % 16 == 0) {
+      dim3 grid(blocks_for(K, 64), blocks_for(N, 64), nsplit);
+      hipLaunchKernelGGL(dw_kernel, grid, dim3(256), 0, s, g);
+      e = hipGetLastError();
+    } else {
+      e = gemm(EPI_PART, g, nsplit, s);
+    }
     if (e != hipSuccess) return e;
     float *gW = gparams + param_off(w, l);
     hipLaunchKernelGGL(reduce_parts_kernel, dim3(blocks_for((int64_t)N * K)), dim3(256), 0, s,
