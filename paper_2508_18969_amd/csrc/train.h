@@ -17,6 +17,7 @@ struct TrainScratch {
   float *out;             // [S][cap] network output
   float *dz[2];           // [max hidden or S][cap] ping-pong gradients
   float *part;            // [nsplit][max layer params] split-K partial sums
+  float *bpart;           // [nsplit][max layer width] bias-gradient partial sums
   float *lpart;           // [1024] loss partial sums
   int nsplit;
 };

@@ -39,6 +39,7 @@ struct GemmArgs {
   const float *bias;       // EPI_FWD: [M]
   const float *zprev;      // EPI_DA: multiply by GELU'(zprev[m * scm + n * scn]) if set
   int64_t part_stride;     // EPI_PART: offset of split z's partial block
+  float *bpart;            // weight-gradient partials: also the row sums of A, [split][M], or NULL
 };
 
 // C = A B over one K-split; 64x64 output tile, four waves of 32x32, the
@@ -116,6 +117,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
 // aligned (leading dimensions multiples of 4).
 __global__ __launch_bounds__(256) void dw_kernel(GemmArgs g) {
   __shared__ float red[2][64][65];
+  __shared__ float rsl[4][4][64];       // row sums of A per wave and lane group
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g4 = lane >> 4, c16 = lane & 15;
   const int64_t m0 = (int64_t)blockIdx.y * 64, n0 = (int64_t)blockIdx.x * 64;
   const int64_t k0 = (int64_t)blockIdx.z * g.kchunk;
@@ -139,6 +141,7 @@ __global__ __launch_bounds__(256) void dw_kernel(GemmArgs g) {
     ra[i] = (va[i] ? m : 0) * g.sam;
     rb[i] = (vb[i] ? n : 0) * g.sbn;
   }
+  float rs[4] = {0.f, 0.f, 0.f, 0.f};        // row sums of A (the bias gradient)
   for (int64_t kb = kb0; kb < kb1; kb += 16) {
     const int64_t k = kb + 4 * g4;
     f4 a[4], b[4];
@@ -158,7 +161,7 @@ __global__ __launch_bounds__(256) void dw_kernel(GemmArgs g) {
         }
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 4; ++i) {
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         if (!va[i]) a[i][e] = 0.0f;
@@ -167,6 +170,8 @@ __global__ __launch_bounds__(256) void dw_kernel(GemmArgs g) {
         // zero past the batch (gelu(0) = 0 as well)
         b[i][e] = (k + e < kb1) ? v : 0.0f;
       }
+      rs[i] += (a[i][0] + a[i][1]) + (a[i][2] + a[i][3]);
+    }
 #pragma unroll
     for (int e = 0; e < 4; ++e)
 #pragma unroll
@@ -174,6 +179,18 @@ __global__ __launch_bounds__(256) void dw_kernel(GemmArgs g) {
 #pragma unroll
         for (int j = 0; j < 4; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][e], b[j][e], acc[i][j], 0, 0, 0);
+  }
+  // row sums: per row, the 16 (wave, lane group) partials in that order
+  if (g.bpart && blockIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) rsl[w][g4][16 * i + c16] = rs[i];
+    __syncthreads();
+    if (tid < 64 && m0 + tid < g.M) {
+      float t = 0.0f;
+      for (int ww = 0; ww < 4; ++ww)
+        for (int gg = 0; gg < 4; ++gg) t += rsl[ww][gg][tid];
+      g.bpart[blockIdx.z * (int64_t)g.M + m0 + tid] = t;
+    }
   }
   // the waves' partial tiles, summed in wave order ((w0 + w1) + w2) + w3,
   // through LDS in two halves
@@ -370,7 +387,11 @@ hipError_t backward(const int *w, int64_t B, const float *x, int64_t ldx, const 
     g.M = N; g.N = K; g.K = B; g.kchunk = kchunk;
     g.part_stride = (int64_t)N * K;
     hipError_t e;
-    if (lddz % 4 == 0 && ldain % 4 == 0 && ((uintptr_t)dZ | (uintptr_t)ain) % 16 == 0) {
+    float *gW = gparams + param_off(w, l);
+    const bool direct = lddz % 4 == 0 && ldain % 4 == 0 && ((uintptr_t)dZ | (uintptr_t)ain) % 16 == 0;
+    if (direct) {
+      // weight and bias partials in one pass
+      g.bpart = t->bpart;
       dim3 grid(blocks_for(K, 64), blocks_for(N, 64), nsplit);
       hipLaunchKernelGGL(dw_kernel, grid, dim3(256), 0, s, g);
       e = hipGetLastError();
@@ -378,10 +399,13 @@ hipError_t backward(const int *w, int64_t B, const float *x, int64_t ldx, const 
       e = gemm(EPI_PART, g, nsplit, s);
     }
     if (e != hipSuccess) return e;
-    float *gW = gparams + param_off(w, l);
     hipLaunchKernelGGL(reduce_parts_kernel, dim3(blocks_for((int64_t)N * K)), dim3(256), 0, s,
                        (const float *)t->part, (int64_t)N * K, nsplit, (int64_t)N * K, gW);
-    hipLaunchKernelGGL(rowsum_kernel, dim3(N), dim3(256), 0, s, dZ, lddz, B, gW + (size_t)N * K);
+    if (direct)
+      hipLaunchKernelGGL(reduce_parts_kernel, dim3(blocks_for(N)), dim3(256), 0, s,
+                         (const float *)t->bpart, (int64_t)N, nsplit, (int64_t)N, gW + (size_t)N * K);
+    else
+      hipLaunchKernelGGL(rowsum_kernel, dim3(N), dim3(256), 0, s, dZ, lddz, B, gW + (size_t)N * K);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // dZ_(l-1) = (W_l^T dZ_l) * GELU'(z_(l-1)), or grad_x for l = 0
     if (l > 0 || gx) {
@@ -412,8 +436,8 @@ size_t train_scratch_bytes(const int *w, int64_t cap) {
   int64_t mx = w[4];
   for (int l = 1; l < 4; ++l) mx = mx > w[l] ? mx : w[l];
   size_t f = (size_t)cap * (w[0] + H + w[4] + 2 * mx) + (size_t)kMaxSplit * max_layer_weights(w) +
-             1024;
-  return f * sizeof(float) + 8 * 256;
+             (size_t)kMaxSplit * mx + 1024;
+  return f * sizeof(float) + 9 * 256;
 }
 
 void train_scratch_layout(TrainScratch *t, uint8_t *base, const int *w, int64_t cap) {
@@ -434,6 +458,7 @@ void train_scratch_layout(TrainScratch *t, uint8_t *base, const int *w, int64_t 
   t->dz[0] = take((size_t)cap * mx);
   t->dz[1] = take((size_t)cap * mx);
   t->part = take((size_t)kMaxSplit * max_layer_weights(w));
+  t->bpart = take((size_t)kMaxSplit * mx);
   t->lpart = take(1024);
   t->act = nullptr;
   t->nsplit = kMaxSplit;
