@@ -225,6 +225,92 @@ __global__ __launch_bounds__(256) void dw_kernel(GemmArgs g) {
   }
 }
 
+// C = A B (+ epilogue) with the batch as the fast index of B and C, for the
+// forward (EPI_FWD: + bias) and the activation gradient (EPI_DA: times
+// GELU'(zprev)).  Workgroup tile 64 rows x 256 columns; wave w takes columns
+// 64 w .. 64 w + 63 of it as four interleaved 16-column blocks (block j holds
+// the columns 4 c + j, c = 0..15), so that every lane loads and stores four
+// consecutive columns with one 16-byte access.  The operand A (weights) is read
+// with plain loads (it is small and cached), B straight from global memory.
+// Requires B and C rows 16-byte aligned (leading dimensions multiples of 4).
+template <int EPI>
+__global__ __launch_bounds__(256) void fc_kernel(GemmArgs g) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g4 = lane >> 4, c16 = lane & 15;
+  const int64_t m0 = (int64_t)blockIdx.y * 64;
+  const int64_t nc = (int64_t)blockIdx.x * 256 + 64 * w + 4 * c16;   // this lane's first column
+  const bool full = nc + 3 < g.N;
+  f4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int64_t k0 = 0; k0 < g.K; k0 += 16) {
+    float a[4][4];
+    f4 b[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t k = k0 + 4 * g4 + e;
+      const bool kv = k < g.K;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t m = m0 + 16 * i + c16;
+        a[i][e] = (kv && m < g.M) ? g.A[m * g.sam + k * g.sak] : 0.0f;
+      }
+      const float *bp = g.B + (kv ? k : 0) * g.sbk;
+      f4 v;
+      if (full) {
+        v = *(const f4 *)(bp + nc);
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = nc + j < g.N ? bp[nc + j] : 0.0f;
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        float x = kv ? v[j] : 0.0f;
+        if (g.gelu_b) x = gelu(x);
+        v[j] = x;
+      }
+      b[e] = v;
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][e], b[e][j], acc[i][j], 0, 0, 0);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t m = m0 + 16 * i + 4 * g4 + r;
+      if (m >= g.M) continue;
+      f4 v = {acc[i][0][r], acc[i][1][r], acc[i][2][r], acc[i][3][r]};
+      if (EPI == EPI_FWD) v += g.bias[m];
+      float *cp = g.C + m * g.scm;
+      if (EPI == EPI_DA && g.zprev) {
+        const float *zp = g.zprev + m * g.scm;
+        if (full) {
+          const f4 z = *(const f4 *)(zp + nc);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) v[j] *= gelu_grad(z[j]);
+        } else {
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            if (nc + j < g.N) v[j] *= gelu_grad(zp[nc + j]);
+        }
+      }
+      if (full) {
+        *(f4 *)(cp + nc) = v;
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (nc + j < g.N) cp[nc + j] = v[j];
+      }
+    }
+}
+
 // out[i] = sum over z of part[z * stride + i], z in increasing order.
 __global__ void reduce_parts_kernel(const float *part, int64_t stride, int nz, int64_t n,
                                     float *out) {
@@ -309,6 +395,15 @@ __global__ void adam_kernel(float *p, const float *g, float *m, float *v, int64_
 unsigned blocks_for(int64_t n, int per = 256) { return (unsigned)((n + per - 1) / per); }
 
 hipError_t gemm(int epi, const GemmArgs &g, int nsplit, hipStream_t s) {
+  // batch-fast products with 16-byte aligned rows: the direct kernel
+  if ((epi == EPI_FWD || epi == EPI_DA) && nsplit == 1 && g.sbn == 1 && g.scn == 1 &&
+      g.sbk % 4 == 0 && g.scm % 4 == 0 && ((uintptr_t)g.B | (uintptr_t)g.C) % 16 == 0 &&
+      (!g.zprev || (uintptr_t)g.zprev % 16 == 0)) {
+    dim3 grid(blocks_for(g.N, 256), blocks_for(g.M, 64));
+    if (epi == EPI_FWD) hipLaunchKernelGGL(fc_kernel<EPI_FWD>, grid, dim3(256), 0, s, g);
+    else hipLaunchKernelGGL(fc_kernel<EPI_DA>, grid, dim3(256), 0, s, g);
+    return hipGetLastError();
+  }
   dim3 grid(blocks_for(g.N, 64), blocks_for(g.M, 64), nsplit);
   switch (epi) {
     case EPI_FWD: hipLaunchKernelGGL(gemm_kernel<EPI_FWD>, grid, dim3(256), 0, s, g); break;
