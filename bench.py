@@ -65,7 +65,8 @@ def main():
                     help="'+table' selects the tabulated GELU")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline leg")
     ap.add_argument("--workloads",
-                    default="fp8_bimodal_2p24,block_2p27,train_b65536,source_2p20,odenet_2p20",
+                    default="fp8_bimodal_2p24,block_2p27,train_b65536,source_2p20,odenet_2p20,"
+                            "prnet_2p20",
                     help="further workloads timed after the headline one ('' for none)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="bytes of one plain device copy run before the timed region")
@@ -407,8 +408,47 @@ def wl_odenet(torch, synth, ChemDNN, n=1 << 20):
     return out, None
 
 
+def wl_prnet(torch, synth, ChemDNN, n=1 << 20):
+    """The property networks of the supercritical flame (the paper's PRNet
+    sizes 3-1024-512-256-1 for the density and 3-2048-1024-512-4 for the
+    temperature and transport properties) over 2^20 cells of the LOX/CH4
+    mixing-layer inputs, in BF16 and FP16, through chem_prop_eval."""
+    from paper_2508_18969_amd import PropNet
+    dev = torch.device("cuda")
+    out = {}
+    for cfg, name in ((7, "density"), (8, "transport")):
+        net = synth.make_prop_net(cfg)
+        x = torch.tensor(synth.make_prop_inputs(cfg, n), device=dev)
+        y = torch.empty((net.widths[-1], n), dtype=torch.float64, device=dev)
+        params = torch.tensor(net.flat_params(), device=dev)
+        flop = 2 * sum(a * b for a, b in zip(net.widths[:-1], net.widths[1:]))
+        res = {"widths": list(net.widths), "flop_per_cell": flop}
+        for prec in ("bf16", "fp16"):
+            h = PropNet(net.widths, prec, params, net.in_mean, net.in_std, net.out_mean, net.out_std)
+            for _ in range(3):
+                h.eval(x, y)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(10):
+                h.eval(x, y)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / 10
+            h.close()
+            tf = flop * n / (ms * 1e-3) * 1e-12
+            res[prec] = {"ms_per_step": ms, "cells_per_s": n / (ms * 1e-3), "tflops": tf,
+                         "mfma_frac": tf / PEAK_TFLOPS[prec]}
+        out[name] = res
+        del x, y, params
+    out["config"] = {"cells": n, "inputs": "E, p, mixture fraction (seeded LOX/CH4 mixing layer)"}
+    torch.cuda.empty_cache()
+    return out, None
+
+
 WORKLOADS = {"fp8_bimodal_2p24": wl_fp8_bimodal, "block_2p27": wl_block, "train_b65536": wl_train,
-             "source_2p20": wl_source, "odenet_2p20": wl_odenet}
+             "source_2p20": wl_source, "odenet_2p20": wl_odenet, "prnet_2p20": wl_prnet}
 
 
 def _counter_means(path, name_part):

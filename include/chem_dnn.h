@@ -74,8 +74,12 @@ enum {
 /* Network and transform description.  All pointers are host pointers; the
  * arrays are copied by chem_dnn_init and need not outlive it. */
 typedef struct {
-    int32_t n_species;          /* S, 1..32 */
-    int32_t n_layers;           /* L linear layers; this build supports L = 4 */
+    int32_t n_species;          /* S, 1..30 */
+    int32_t n_layers;           /* L linear layers, 1..8.  Built: L = 4 with the hidden widths
+                                   of the fused kernel (19-400-200-100-17, 31-1600-800-400-29,
+                                   all precisions, training), and 2..8 layers with hidden
+                                   widths that are multiples of 256 (layer by layer; FP32, BF16,
+                                   FP16, tanh GELU, inference only); EUNSUPPORTED otherwise */
     int32_t widths[9];          /* widths[0] = S + 2, widths[L] = S, hidden widths 1..4096 */
     int32_t precision;          /* CHEM_DNN_FP32 / _BF16 / _FP16 / _FP8E4M3 */
     int32_t gelu_form;          /* CHEM_DNN_GELU_TANH or CHEM_DNN_GELU_TABLE (hidden layers of
@@ -187,11 +191,67 @@ int32_t chem_dnn_train_step(chem_dnn *h, int64_t B, int64_t ld, const double *T,
 /* Release the handle (host memory only; the caller frees the workspace). */
 int32_t chem_dnn_destroy(chem_dnn *h);
 
+/* ------------------------------------------------------------------------
+ * Property networks.  For flames at supercritical pressure a second network
+ * per cell (the paper's PRNet, Sec. 2; sizes 3-1024-512-256-1 for the density
+ * and 3-2048-1024-512-4 for the temperature and transport properties, Sec. 4)
+ * maps a few thermodynamic state variables to mixture properties in place of
+ * the real-fluid equation of state.  chem_prop_eval performs, for every cell:
+ *
+ *   1. z = (x - mu_in) / sigma_in          (FP64, then FP32 operands)
+ *   2. a_l = GELU(W_l a_(l-1) + b_l), l < L;  o = W_L a_(L-1) + b_L
+ *      (the GELU, operand formats and FP32 accumulation of chem_dnn_step)
+ *   3. y = o sigma_out + mu_out            (FP64)
+ *
+ * Cells are independent; a non-finite input gives non-finite outputs of that
+ * cell only.  Conventions (status codes, streams, ownership, SoA layout) are
+ * those of the chemistry entry points above.
+ * ------------------------------------------------------------------------ */
+typedef struct chem_prop chem_prop; /* opaque handle; host memory owned by the library */
+
+typedef struct {
+    int32_t n_layers;           /* L linear layers, 2..8 */
+    int32_t widths[9];          /* widths[0] = number of inputs 1..32, widths[L] = number of
+                                   outputs 1..32, hidden widths multiples of 256 up to 4096 */
+    int32_t precision;          /* CHEM_DNN_FP32 / _BF16 / _FP16 (FP8: EUNSUPPORTED) */
+    const double *in_mean;      /* host [widths[0]] input mean */
+    const double *in_std;       /* host [widths[0]] input standard deviation, > 0 */
+    const double *out_mean;     /* host [widths[L]] output mean; NULL -> 0 */
+    const double *out_std;      /* host [widths[L]] output scale; NULL -> 1 */
+} chem_prop_desc;
+
+/* Device workspace for `desc`: packed weights, constants and the activation
+ * buffers of one chunk of cells.  EINVAL for a bad description,
+ * EUNSUPPORTED for a shape or precision this build lacks. */
+int32_t chem_prop_workspace_bytes(const chem_prop_desc *desc, size_t *bytes);
+
+/* Create a handle on the current HIP device; params (device FP32, flat
+ * [W_1 (out x in, row-major), b_1, ..., W_L, b_L]) is packed into the
+ * workspace (device, 256-byte aligned, >= chem_prop_workspace_bytes), which
+ * stays allocated and unmodified until chem_prop_destroy.  The host arrays of
+ * the description are copied.  ENODEV / EUNSUPPORTED as chem_dnn_init. */
+int32_t chem_prop_init(const chem_prop_desc *desc, const float *params, void *workspace,
+                       size_t workspace_bytes, void *stream, chem_prop **out);
+
+/* Re-pack the weights from a new FP32 parameter vector (device). */
+int32_t chem_prop_set_params(chem_prop *h, const float *params, void *stream);
+
+/* Evaluate the network on n cells:
+ *   x   device FP64 [widths[0]][ld]   input fields
+ *   y   device FP64 [widths[L]][ld]   outputs; must not alias x
+ * n = 0 is a no-op. */
+int32_t chem_prop_eval(chem_prop *h, int64_t n, int64_t ld, const double *x, double *y,
+                       void *stream);
+
+/* Release the handle (host memory only). */
+int32_t chem_prop_destroy(chem_prop *h);
+
 /* Static description of a status code. */
 const char *chem_dnn_strerror(int32_t status);
 
-/* ABI version of this header: 3 (2 added gelu_form to chem_dnn_desc; 3 added
- * molar_mass at its end and chem_dnn_step_source). */
+/* ABI version of this header: 4 (2 added gelu_form to chem_dnn_desc; 3 added
+ * molar_mass at its end and chem_dnn_step_source; 4 added the property
+ * networks, chem_prop_*). */
 int32_t chem_dnn_abi_version(void);
 
 #ifdef __cplusplus

@@ -14,6 +14,8 @@ Contents
              enthalpy-conserving temperature; exact FP64 and an emulation of
              narrow operand formats (bf16, f16, OCP e4m3) with power-of-two
              per-layer scales.
+``prop``     the property networks (PRNet): Z-score of the input fields,
+             the same MLP, and the output scaling.
 ``train``    MLP forward with saved pre-activations, MSE loss, hand-derived
              backward, Adam.
 ``kinetics`` mass-action kinetics of an ideal-gas constant-pressure

@@ -22,7 +22,8 @@ PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp16": FP16, "fp8": FP8E4M3}
 EXPORTS = ("chem_dnn_workspace_bytes", "chem_dnn_init", "chem_dnn_set_params", "chem_dnn_step",
            "chem_dnn_step_source", "chem_dnn_calibrate", "chem_dnn_get_scales", "chem_dnn_mlp_forward",
            "chem_dnn_mlp_backward", "chem_dnn_train_step", "chem_dnn_destroy",
-           "chem_dnn_strerror", "chem_dnn_abi_version")
+           "chem_dnn_strerror", "chem_dnn_abi_version", "chem_prop_workspace_bytes",
+           "chem_prop_init", "chem_prop_set_params", "chem_prop_eval", "chem_prop_destroy")
 
 _dp = C.POINTER(C.c_double)
 _fp = C.POINTER(C.c_float)
@@ -34,6 +35,11 @@ class Desc(C.Structure):
                 ("in_mean", _dp), ("in_std", _dp), ("out_mean", _dp), ("out_std", _dp),
                 ("act_amax", _fp), ("thermo_hf", _dp), ("thermo_cp", _dp), ("t_ref", C.c_double),
                 ("max_batch", C.c_int64), ("molar_mass", _dp)]
+
+
+class PropDesc(C.Structure):
+    _fields_ = [("n_layers", C.c_int32), ("widths", C.c_int32 * 9), ("precision", C.c_int32),
+                ("in_mean", _dp), ("in_std", _dp), ("out_mean", _dp), ("out_std", _dp)]
 
 
 class ChemDNNError(RuntimeError):
@@ -67,6 +73,11 @@ def lib():
         L.chem_dnn_train_step.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp, i64,
                                           C.c_float, C.c_int32, vp, vp]
         L.chem_dnn_destroy.argtypes = [vp]
+        L.chem_prop_workspace_bytes.argtypes = [C.POINTER(PropDesc), C.POINTER(C.c_size_t)]
+        L.chem_prop_init.argtypes = [C.POINTER(PropDesc), vp, vp, C.c_size_t, vp, C.POINTER(vp)]
+        L.chem_prop_set_params.argtypes = [vp, vp, vp]
+        L.chem_prop_eval.argtypes = [vp, i64, i64, vp, vp, vp]
+        L.chem_prop_destroy.argtypes = [vp]
         L.chem_dnn_strerror.argtypes = [C.c_int32]
         L.chem_dnn_strerror.restype = C.c_char_p
         for name in EXPORTS:
@@ -308,6 +319,85 @@ class ChemDNN:
     def close(self):
         if getattr(self, "_h", None):
             lib().chem_dnn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def make_prop_desc(widths, precision, in_mean, in_std, out_mean=None, out_std=None):
+    """Fills a PropDesc; returns (desc, keepalive)."""
+    d = PropDesc()
+    widths = [int(w) for w in widths]
+    d.n_layers = len(widths) - 1
+    for i, w in enumerate(widths):
+        d.widths[i] = w
+    d.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    keep = []
+    for name, val in (("in_mean", in_mean), ("in_std", in_std), ("out_mean", out_mean),
+                      ("out_std", out_std)):
+        a, ptr = _arr(val, C.c_double)
+        keep.append(a)
+        setattr(d, name, ptr)
+    return d, keep
+
+
+def prop_workspace_bytes(desc) -> int:
+    n = C.c_size_t(0)
+    _check(lib().chem_prop_workspace_bytes(C.byref(desc), C.byref(n)), "chem_prop_workspace_bytes")
+    return int(n.value)
+
+
+class PropNet:
+    """A property-network handle (chem_prop_*) on the current device: inputs
+    x [n_in][ld] -> outputs y [n_out][ld], both float64.
+
+    params: CUDA float32 tensor, flat [W1 (out x in), b1, ..., WL, bL].
+    """
+
+    def __init__(self, widths, precision, params, in_mean, in_std, out_mean=None, out_std=None):
+        import torch
+        self.widths = tuple(int(w) for w in widths)
+        self.n_in, self.n_out = self.widths[0], self.widths[-1]
+        self.precision = precision
+        desc, keep = make_prop_desc(self.widths, precision, in_mean, in_std, out_mean, out_std)
+        nbytes = prop_workspace_bytes(desc)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=params.device)
+        base = self.workspace.data_ptr()
+        ws = base + (-base) % 256
+        h = C.c_void_p()
+        _check(lib().chem_prop_init(C.byref(desc), _ptr(params), C.c_void_p(ws), C.c_size_t(nbytes),
+                                    _stream(), C.byref(h)), "chem_prop_init")
+        self._h = h
+        del keep
+
+    def eval(self, x, y=None):
+        """Outputs of n cells for inputs x (float64 [n_in][ld])."""
+        import torch
+        n = int(x.shape[1])
+        # the common leading dimension (a one-row field does not fix it)
+        if self.n_in > 1:
+            ld = int(x.stride(0))
+        elif y is not None and self.n_out > 1:
+            ld = int(y.stride(0))
+        else:
+            ld = n
+        if y is None:
+            y = torch.empty((self.n_out, ld), dtype=torch.float64, device=x.device)[:, :n]
+        _check_field(x, "x", self.n_in, n, ld, torch.float64)
+        _check_field(y, "y", self.n_out, n, ld, torch.float64)
+        _check(lib().chem_prop_eval(self._h, n, ld, _ptr(x), _ptr(y), _stream()), "chem_prop_eval")
+        return y
+
+    def set_params(self, params):
+        _check(lib().chem_prop_set_params(self._h, _ptr(params), _stream()), "chem_prop_set_params")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().chem_prop_destroy(self._h)
             self._h = None
 
     def __del__(self):

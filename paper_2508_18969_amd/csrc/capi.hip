@@ -43,6 +43,21 @@ struct chem_dnn {
   float hgtab[GTAB_N * 4];
 };
 
+// Property-network handle (layer-by-layer path only).
+struct chem_prop {
+  int L, prec, widths[9];
+  int lR[8], lNQ[8];     // per layer: output row-blocks, input k-steps
+  int64_t chunk;         // cells per chunk
+  uint8_t *ws;
+  size_t ws_bytes;
+  double *pc;            // PConst block
+  float *bias[8];
+  void *wpack[8];
+  uint8_t *act[2];       // activation fragment buffers of one chunk
+  float *obuf;           // FP32 network output of one chunk [32][chunk]
+  double hpc[PConst::N]; // host copy kept alive for the asynchronous upload
+};
+
 namespace {
 
 constexpr size_t kAlign = 256;
@@ -275,6 +290,87 @@ int32_t run_layered(chem_dnn *h, int64_t n, int64_t ld, const double *T, const d
   return hip_status(e);
 }
 
+// ---- property networks
+int32_t check_prop_desc(const chem_prop_desc *d) {
+  if (!d) return CHEM_DNN_EINVAL;
+  const int L = d->n_layers;
+  if (L < 2 || L > 8) return CHEM_DNN_EINVAL;
+  const int D = d->widths[0], K = d->widths[L];
+  if (D < 1 || D > 32 || K < 1 || K > 32) return CHEM_DNN_EINVAL;
+  for (int l = 1; l < L; ++l)
+    if (d->widths[l] < 1 || d->widths[l] > 4096) return CHEM_DNN_EINVAL;
+  if (d->precision < CHEM_DNN_FP32 || d->precision > CHEM_DNN_FP8E4M3) return CHEM_DNN_EINVAL;
+  if (!d->in_mean || !d->in_std) return CHEM_DNN_EINVAL;
+  for (int f = 0; f < D; ++f)
+    if (!(d->in_std[f] > 0.0) || !isfinite(d->in_mean[f]) || !isfinite(d->in_std[f]))
+      return CHEM_DNN_EINVAL;
+  for (int k = 0; k < K; ++k)
+    if ((d->out_mean && !isfinite(d->out_mean[k])) || (d->out_std && !isfinite(d->out_std[k])))
+      return CHEM_DNN_EINVAL;
+  if (d->precision == CHEM_DNN_FP8E4M3) return CHEM_DNN_EUNSUPPORTED;
+  for (int l = 1; l < L; ++l)
+    if (d->widths[l] % 256) return CHEM_DNN_EUNSUPPORTED;   // the layer kernel's row tiles
+  return CHEM_DNN_OK;
+}
+
+// Cells per chunk: doubled from kChunk (up to 4 kChunk) while the widest
+// hidden activation of a chunk stays within 128 MiB, so that narrow networks
+// give the layer kernel enough cell tiles and the chunk's activations still
+// fit the last-level cache.
+int64_t prop_chunk(const chem_prop_desc *d) {
+  int hmax = 1;
+  for (int l = 1; l < d->n_layers; ++l) hmax = d->widths[l] > hmax ? d->widths[l] : hmax;
+  const int64_t cap = (int64_t)128 << 20;
+  int64_t c = kChunk;
+  while (c < 4 * kChunk && 2 * c * hmax * eb_of(d->precision) <= cap) c *= 2;
+  return c;
+}
+
+struct PropPlan {
+  size_t pc, bias[8], w[8], act[2], obuf, total;
+  int64_t chunk;
+};
+
+int32_t prop_plan(const chem_prop_desc *d, PropPlan *p) {
+  int32_t st = check_prop_desc(d);
+  if (st) return st;
+  const int L = d->n_layers, ks = ks_of(d->precision), eb = eb_of(d->precision);
+  p->chunk = prop_chunk(d);
+  size_t off = 0;
+  p->pc = off; off = align_up(off + PConst::N * sizeof(double));
+  int kmax = 32;
+  for (int l = 0; l < L; ++l) {
+    const int R = l == L - 1 ? 2 : d->widths[l + 1] / 16;   // output layer: 32 rows
+    const int K = l == 0 ? 32 : d->widths[l];
+    kmax = K > kmax ? K : kmax;
+    p->bias[l] = off;
+    off = align_up(off + (size_t)R * 16 * sizeof(float));
+    p->w[l] = off;
+    off = align_up(off + (size_t)R * 16 * (K / ks) * ks * eb);
+  }
+  for (int b = 0; b < 2; ++b) {
+    p->act[b] = off;
+    off = align_up(off + (size_t)kmax * p->chunk * eb);
+  }
+  p->obuf = off;
+  off = align_up(off + (size_t)32 * p->chunk * sizeof(float));
+  p->total = off;
+  return CHEM_DNN_OK;
+}
+
+int32_t prop_pack(chem_prop *h, const float *params, hipStream_t s) {
+  hipError_t e = hipSuccess;
+  for (int l = 0; l < h->L && e == hipSuccess; ++l) {
+    const int N = h->widths[l + 1], K = h->widths[l];
+    e = launch_pack(params + param_offset(h->widths, l, false), N, K, 0, h->lR[l], h->lNQ[l],
+                    ks_of(h->prec), h->prec, nullptr, h->wpack[l], s);
+    if (e == hipSuccess)
+      e = launch_pad_bias(params + param_offset(h->widths, l, true), N, 0, h->lR[l] * 16,
+                          h->bias[l], s);
+  }
+  return hip_status(e);
+}
+
 int grid_for(const chem_dnn *h, int64_t ntiles) {
   int64_t g = ntiles < h->n_cu ? ntiles : h->n_cu;
   return (int)(g < 1 ? 1 : g);
@@ -284,7 +380,7 @@ int grid_for(const chem_dnn *h, int64_t ntiles) {
 
 extern "C" {
 
-int32_t chem_dnn_abi_version(void) { return 3; }
+int32_t chem_dnn_abi_version(void) { return 4; }
 
 const char *chem_dnn_strerror(int32_t st) {
   switch (st) {
@@ -530,6 +626,118 @@ int32_t chem_dnn_train_step(chem_dnn *h, int64_t B, int64_t ld, const double *T,
 }
 
 int32_t chem_dnn_destroy(chem_dnn *h) {
+  if (!h) return CHEM_DNN_EINVAL;
+  delete h;
+  return CHEM_DNN_OK;
+}
+
+int32_t chem_prop_workspace_bytes(const chem_prop_desc *desc, size_t *bytes) {
+  if (!bytes) return CHEM_DNN_EINVAL;
+  PropPlan p;
+  int32_t st = prop_plan(desc, &p);
+  if (st) return st;
+  *bytes = p.total;
+  return CHEM_DNN_OK;
+}
+
+int32_t chem_prop_init(const chem_prop_desc *d, const float *params, void *workspace,
+                       size_t workspace_bytes, void *stream, chem_prop **out) {
+  if (!out) return CHEM_DNN_EINVAL;
+  *out = nullptr;
+  PropPlan p;
+  int32_t st = prop_plan(d, &p);
+  if (st) return st;
+  if (!params) return CHEM_DNN_EINVAL;
+  if (!workspace || ((uintptr_t)workspace % kAlign) || workspace_bytes < p.total)
+    return CHEM_DNN_EWORKSPACE;
+  int dev = 0, n_cu = 0;
+  st = current_device(&dev, &n_cu);
+  if (st) return st;
+  if (layered_prepare() != hipSuccess) return CHEM_DNN_EHIP;
+  chem_prop *h = new (std::nothrow) chem_prop();
+  if (!h) return CHEM_DNN_EHIP;
+  h->L = d->n_layers;
+  h->prec = d->precision;
+  for (int l = 0; l <= h->L; ++l) h->widths[l] = d->widths[l];
+  const int ks = ks_of(d->precision);
+  for (int l = 0; l < h->L; ++l) {
+    h->lR[l] = l == h->L - 1 ? 2 : d->widths[l + 1] / 16;
+    h->lNQ[l] = (l == 0 ? 32 : d->widths[l]) / ks;
+  }
+  h->chunk = p.chunk;
+  h->ws = (uint8_t *)workspace;
+  h->ws_bytes = workspace_bytes;
+  h->pc = (double *)(h->ws + p.pc);
+  for (int l = 0; l < h->L; ++l) {
+    h->bias[l] = (float *)(h->ws + p.bias[l]);
+    h->wpack[l] = h->ws + p.w[l];
+  }
+  h->act[0] = h->ws + p.act[0];
+  h->act[1] = h->ws + p.act[1];
+  h->obuf = (float *)(h->ws + p.obuf);
+  memset(h->hpc, 0, sizeof(h->hpc));
+  for (int f = 0; f < d->widths[0]; ++f) {
+    h->hpc[PConst::IN_MU + f] = d->in_mean[f];
+    h->hpc[PConst::IN_IS + f] = 1.0 / d->in_std[f];
+  }
+  for (int k = 0; k < d->widths[h->L]; ++k) {
+    h->hpc[PConst::OUT_MU + k] = d->out_mean ? d->out_mean[k] : 0.0;
+    h->hpc[PConst::OUT_SD + k] = d->out_std ? d->out_std[k] : 1.0;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  st = hip_status(hipMemcpyAsync(h->pc, h->hpc, sizeof(h->hpc), hipMemcpyHostToDevice, s));
+  if (st == CHEM_DNN_OK) st = prop_pack(h, params, s);
+  // the host copy must not be released before the upload finishes
+  if (st == CHEM_DNN_OK && hipStreamSynchronize(s) != hipSuccess) st = CHEM_DNN_EHIP;
+  if (st) {
+    delete h;
+    return st;
+  }
+  *out = h;
+  return CHEM_DNN_OK;
+}
+
+int32_t chem_prop_set_params(chem_prop *h, const float *params, void *stream) {
+  if (!h || !params) return CHEM_DNN_EINVAL;
+  return prop_pack(h, params, (hipStream_t)stream);
+}
+
+int32_t chem_prop_eval(chem_prop *h, int64_t n, int64_t ld, const double *x, double *y,
+                       void *stream) {
+  if (!h || n < 0 || ld < n) return CHEM_DNN_EINVAL;
+  if (n == 0) return CHEM_DNN_OK;
+  if (!x || !y) return CHEM_DNN_EINVAL;
+  const int D = h->widths[0], K = h->widths[h->L];
+  {  // x [D][ld] and y [K][ld] must not overlap
+    const uintptr_t x0 = (uintptr_t)x, x1 = (uintptr_t)(x + (D - 1) * ld + n);
+    const uintptr_t y0 = (uintptr_t)y, y1 = (uintptr_t)(y + (K - 1) * ld + n);
+    if (x0 < y1 && y0 < x1) return CHEM_DNN_EINVAL;
+  }
+  const uint8_t *end = h->ws + h->ws_bytes;
+  if ((const uint8_t *)(h->obuf + 32 * h->chunk) > end) return CHEM_DNN_EWORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipSuccess;
+  for (int64_t n0 = 0; n0 < n && e == hipSuccess; n0 += h->chunk) {
+    const int nc = (int)(n - n0 < h->chunk ? n - n0 : h->chunk);
+    const int ncb = (nc + 255) / 256 * 16;     // whole 256-cell tiles
+    PropPrepArgs pa{x, ld, n0, nc, ncb, D, h->act[0], h->pc};
+    e = launch_prop_prep(h->prec, pa, s);
+    int cur = 0;
+    for (int l = 0; l < h->L && e == hipSuccess; ++l) {
+      LayerArgs la{(const uint8_t *)h->wpack[l], h->bias[l], h->act[cur], h->act[cur ^ 1],
+                   h->obuf, h->lR[l], h->lNQ[l], ncb, 16 * ncb};
+      e = launch_layer(h->prec, la, l < h->L - 1, s);
+      cur ^= 1;
+    }
+    if (e == hipSuccess) {
+      PropPostArgs po{y, ld, n0, nc, K, 16 * ncb, h->obuf, h->pc};
+      e = launch_prop_post(po, s);
+    }
+  }
+  return hip_status(e);
+}
+
+int32_t chem_prop_destroy(chem_prop *h) {
   if (!h) return CHEM_DNN_EINVAL;
   delete h;
   return CHEM_DNN_OK;

@@ -86,11 +86,37 @@ struct PostArgs {
   double inv_dt;
   int S, thermo;
 };
+// Property networks: FP64 constants of the input and output affine maps.
+struct PConst {
+  enum {
+    IN_MU = 0,     // [32] input mean
+    IN_IS = 32,    // [32] 1 / input standard deviation
+    OUT_MU = 64,   // [32] output mean
+    OUT_SD = 96,   // [32] output standard deviation
+    N = 128
+  };
+};
+struct PropPrepArgs {
+  const double *x;       // input fields [D][ld]
+  int64_t ld, n0;        // field stride; first cell of the chunk
+  int nc, NCB, D;        // cells of the chunk; cell-blocks written; input count
+  uint8_t *X;            // layer-1 B fragments [32 / KS][NCB]
+  const double *pc;      // PConst block
+};
+struct PropPostArgs {
+  double *y;             // outputs [K][ld]
+  int64_t ld, n0;
+  int nc, K, ldo;        // cells of the chunk; outputs; O's stride
+  const float *O;        // network output [K][ldo] of the chunk
+  const double *pc;
+};
 // fmt: 0 FP32, 1 BF16, 2 FP16 operands
 hipError_t layered_prepare();
 hipError_t launch_prep(int fmt, const PrepArgs &a, hipStream_t s);
 hipError_t launch_layer(int fmt, const LayerArgs &a, bool hidden, hipStream_t s);
 hipError_t launch_post(const PostArgs &a, hipStream_t s);
+hipError_t launch_prop_prep(int fmt, const PropPrepArgs &a, hipStream_t s);
+hipError_t launch_prop_post(const PropPostArgs &a, hipStream_t s);
 
 // Shape and layout of one compiled network configuration.
 struct NetLayout {

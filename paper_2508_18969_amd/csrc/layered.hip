@@ -12,6 +12,12 @@
 //                  output goes straight into the next layer's B fragments
 //   post_kernel    steps 4-7 per cell (one thread per cell, FP64 update)
 //
+// The property networks of the supercritical flame (PRNet, Sec. 2 and the
+// network sizes of Sec. 4: 3-1024-512-256-1 and 3-2048-1024-512-4) run on the
+// same layer kernel between their own input and output maps
+// (prop_prep_kernel: Z-score of the input fields; prop_post_kernel: the
+// output affine map in FP64).
+//
 // Activations live in HBM between layers as "B fragments": for k-step q and
 // cell-block cb (16 cells) a 1 KiB block of 64 lanes x 16 bytes, lane
 // (cell cl, group g) holding input features frag_feature(KS, q, g, j); blocks
@@ -186,6 +192,28 @@ __global__ __launch_bounds__(WR * WC * 64, 1) void layer_kernel(LayerArgs a) {
 }
 
 // ------------------------------------------------------------------ prep
+// Writes the 32 features z of cell c of the chunk into the layer-1 B
+// fragments X ([32 / KS][NCB] fragments).
+template <class Op>
+__device__ __forceinline__ void store_layer1(const float (&z)[32], uint8_t *X, int NCB, int c) {
+  const int cb = c >> 4, cl = c & 15;
+  constexpr int NE = 16 / Op::EB;                          // slots per lane
+#pragma unroll
+  for (int q = 0; q < 32 / Op::KS; ++q)
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      __attribute__((aligned(16))) uint8_t buf[16];
+#pragma unroll
+      for (int j0 = 0; j0 < NE; j0 += 4) {
+        f4 y;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) y[r] = z[frag_feature(Op::KS, q, g, j0 + r)];
+        Op::store4(buf + j0 * Op::EB, y);
+      }
+      *(i4 *)(X + ((size_t)q * NCB + cb) * FB + (g * 16 + cl) * 16) = *(const i4 *)buf;
+    }
+}
+
 // Thread per cell c of the chunk (cells past the chunk give zero features):
 // z_f of steps 1-2 for f < 32, written into the layer-1 B fragments.
 template <class Op>
@@ -212,22 +240,25 @@ __global__ __launch_bounds__(256) void prep_kernel(PrepArgs a) {
     }
     z[f] = v;
   }
-  const int cb = c >> 4, cl = c & 15;
-  constexpr int NE = 16 / Op::EB;                          // slots per lane
+  store_layer1<Op>(z, a.X, a.NCB, c);
+}
+
+// Property network input: thread per cell c of the chunk, z_f = (x_f - mu_f) /
+// sigma_f in FP64 for the n_in input fields (zero for f >= n_in and for cells
+// past the chunk), rounded to FP32 and written into the layer-1 B fragments.
+template <class Op>
+__global__ __launch_bounds__(256) void prop_prep_kernel(PropPrepArgs a) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= 16 * a.NCB) return;
+  const bool valid = c < a.nc;
+  const int64_t i = valid ? a.n0 + c : 0;
+  float z[32];
 #pragma unroll
-  for (int q = 0; q < 32 / Op::KS; ++q)
-#pragma unroll
-    for (int g = 0; g < 4; ++g) {
-      __attribute__((aligned(16))) uint8_t buf[16];
-#pragma unroll
-      for (int j0 = 0; j0 < NE; j0 += 4) {
-        f4 y;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) y[r] = z[frag_feature(Op::KS, q, g, j0 + r)];
-        Op::store4(buf + j0 * Op::EB, y);
-      }
-      *(i4 *)(a.X + ((size_t)q * a.NCB + cb) * FB + (g * 16 + cl) * 16) = *(const i4 *)buf;
-    }
+  for (int f = 0; f < 32; ++f)
+    z[f] = (valid && f < a.D)
+               ? (float)((a.x[(int64_t)f * a.ld + i] - a.pc[PConst::IN_MU + f]) * a.pc[PConst::IN_IS + f])
+               : 0.0f;
+  store_layer1<Op>(z, a.X, a.NCB, c);
 }
 
 // ------------------------------------------------------------------ post
@@ -284,6 +315,15 @@ __global__ __launch_bounds__(256) void post_kernel(PostArgs a) {
   }
   if (a.T_out) a.T_out[i] = okc ? Tn : T;
   if (!okc && a.n_bad) atomicAdd(a.n_bad, 1u);
+}
+
+// Property network output: y_k = o_k sigma_k + mu_k in FP64, thread per
+// (output k, cell c); FP32 network output O[k][ldo] of the chunk.
+__global__ __launch_bounds__(256) void prop_post_kernel(PropPostArgs a) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x, k = blockIdx.y;
+  if (c >= a.nc) return;
+  const double o = a.O[(size_t)k * a.ldo + c];
+  a.y[(int64_t)k * a.ld + a.n0 + c] = __builtin_fma(o, a.pc[PConst::OUT_SD + k], a.pc[PConst::OUT_MU + k]);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -349,6 +389,23 @@ hipError_t launch_prep(int fmt, const PrepArgs &a, hipStream_t s) {
     case 2: hipLaunchKernelGGL(prep_kernel<OpF16>, dim3(blocks), dim3(256), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_prop_prep(int fmt, const PropPrepArgs &a, hipStream_t s) {
+  const int blocks = (16 * a.NCB + 255) / 256;
+  switch (fmt) {
+    case 0: hipLaunchKernelGGL(prop_prep_kernel<OpF32>, dim3(blocks), dim3(256), 0, s, a); break;
+    case 1: hipLaunchKernelGGL(prop_prep_kernel<OpBF16>, dim3(blocks), dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL(prop_prep_kernel<OpF16>, dim3(blocks), dim3(256), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_prop_post(const PropPostArgs &a, hipStream_t s) {
+  if (a.nc <= 0 || a.K <= 0) return hipSuccess;
+  hipLaunchKernelGGL(prop_post_kernel, dim3((a.nc + 255) / 256, a.K), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

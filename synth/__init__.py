@@ -44,6 +44,17 @@ NET_LARGE = (31, 1600, 800, 400, 29)    # 29 species
 NET_ODENET = (19, 2048, 4096, 2048, 1024, 512, 17)
 BOXCOX_LAMBDA = 0.1
 
+# Property networks of the supercritical flame (the paper's PRNet, Sec. 4
+# network sizes): three inputs -> density, and three inputs -> temperature and
+# three transport properties.  Workloads 7 and 8.
+NET_PRNET_RHO = (3, 1024, 512, 256, 1)
+NET_PRNET_TRANS = (3, 2048, 1024, 512, 4)
+PROP_NETS = {7: NET_PRNET_RHO, 8: NET_PRNET_TRANS}
+# Output scales (mean, std) of the properties: density kg/m^3; temperature K,
+# viscosity Pa s, thermal diffusivity m^2/s, thermal conductivity W/(m K).
+PROP_OUT = {7: ([600.0], [350.0]),
+            8: ([1500.0, 4.0e-5, 1.0e-6, 0.1], [900.0, 3.0e-5, 8.0e-7, 0.06])}
+
 T_UNIFORM = (300.0, 3000.0)        # K
 P_MEDIAN, P_SIGMA = 1.0e7, 0.3     # Pa, lognormal
 DIRICHLET_ALPHA = 0.5
@@ -51,7 +62,8 @@ DIRICHLET_ALPHA = 0.5
 
 def streams(config: int) -> dict:
     """Named independent generators for workload ``config`` (1..5; 6 is the
-    paper-size ODENet over the states of workload 1)."""
+    paper-size ODENet over the states of workload 1; 7 and 8 the property
+    networks)."""
     ss = np.random.SeedSequence(SEED_BASE + 1000 * int(config))
     kids = ss.spawn(len(STREAMS))
     return {name: np.random.Generator(np.random.PCG64(k)) for name, k in zip(STREAMS, kids)}
@@ -297,6 +309,44 @@ def make_state(config: int, n: int, stream: str = "inputs", S: int | None = None
             raise ValueError("config 5 needs a cube cell count")
         return draw_block_state(rng, S, edge)
     return draw_uniform_state(rng, S, n)
+
+
+def draw_prop_inputs(rng, n: int) -> np.ndarray:
+    """Inputs of the property networks, [3][n] float64: specific internal
+    energy E (J/kg), pressure p (Pa) and mixture fraction xi of a LOX/CH4
+    mixing layer.  xi ~ Beta(0.5, 0.5) (most cells near one of the two
+    streams), a reaction progress c ~ U(0, 1), E = -3.5e6 (1 - xi) - 1.0e6 xi
+    + 2.5e6 c, and p lognormal around 10 MPa (sigma 0.3) as for the chemistry
+    states."""
+    xi = rng.beta(0.5, 0.5, size=n)
+    c = rng.uniform(0.0, 1.0, size=n)
+    E = -3.5e6 * (1.0 - xi) - 1.0e6 * xi + 2.5e6 * c
+    p = P_MEDIAN * np.exp(P_SIGMA * rng.standard_normal(n))
+    return np.vstack([E, p, xi])
+
+
+def make_prop_inputs(config: int, n: int, stream: str = "inputs") -> np.ndarray:
+    """Seeded property-network inputs of workload 7 or 8 (n cells)."""
+    if config not in PROP_NETS:
+        raise ValueError("property workloads are 7 and 8")
+    return draw_prop_inputs(streams(config)[stream], n)
+
+
+def make_prop_net(config: int, widths=None, bias_scale: float = 0.0) -> Net:
+    """Random-init property network of workload 7 (density) or 8 (temperature
+    and transport properties): Xavier weights, input Z-score statistics (FP64
+    mean, population std) of a 65,536-cell calibration draw, and the stated
+    output scales."""
+    if widths is None:
+        widths = PROP_NETS[config]
+    rng = streams(config)["weights"]
+    W, b = xavier_weights(rng, widths, bias_scale)
+    cal = make_prop_inputs(config, 65536, stream="calibration")
+    om, osd = PROP_OUT[config]
+    K = widths[-1]
+    om = np.resize(np.asarray(om, np.float64), K)
+    osd = np.resize(np.asarray(osd, np.float64), K)
+    return Net(tuple(widths), W, b, cal.mean(axis=1), cal.std(axis=1), om, osd)
 
 
 def make_thermo(config: int, S: int):

@@ -22,12 +22,13 @@ def L():
 
 
 def test_header_declares_what_the_library_exports(L):
-    decl = set(re.findall(r"\b(chem_dnn_[a-z_]+)\s*\(", open(HEADER).read()))
+    decl = set(re.findall(r"\b(chem_(?:dnn|prop)_[a-z_]+)\s*\(", open(HEADER).read()))
     assert decl == set(L.EXPORTS)
+    assert {"chem_prop_init", "chem_prop_eval"} <= decl
     lib = L.lib()
     for name in decl:
         assert hasattr(lib, name), name
-    assert lib.chem_dnn_abi_version() == 3
+    assert lib.chem_dnn_abi_version() == 4
     for st in (0, -1, -2, -3, -4, -5):
         assert L.strerror(st) and L.strerror(st) != "unknown status"
 
@@ -115,3 +116,45 @@ def test_layered_shapes_workspace_and_limits(L):
         with pytest.raises(L.ChemDNNError) as e:
             L.workspace_bytes(d2)
         assert e.value.status == L.EUNSUPPORTED, kw
+
+
+def test_property_networks_workspace_and_validation(L):
+    """The property networks (3-1024-512-256-1, 3-2048-1024-512-4): workspace
+    of the packed weights, two chunk-sized activation buffers and the FP32
+    output buffer; bad descriptions are EINVAL, shapes and formats this build
+    lacks EUNSUPPORTED; null handles are rejected."""
+    lib = L.lib()
+    for cfg, chunk_bf16 in ((7, 65536), (8, 32768)):
+        net = synth.make_prop_net(cfg)
+        d, keep = L.make_prop_desc(net.widths, "bf16", net.in_mean, net.in_std, net.out_mean, net.out_std)
+        n = L.prop_workspace_bytes(d)
+        hmax = max(net.widths[1:-1])
+        weights = 2 * sum(a * b for a, b in zip((32,) + net.widths[1:-1], net.widths[1:-1] + (32,)))
+        assert n >= weights + 2 * hmax * chunk_bf16 * 2 + 32 * chunk_bf16 * 4
+        assert n < weights + 2 * hmax * 2 * chunk_bf16 * 2     # the chunk is not larger
+        d32, k32 = L.make_prop_desc(net.widths, "fp32", net.in_mean, net.in_std)
+        assert L.prop_workspace_bytes(d32) >= 2 * weights + 2 * hmax * 32768 * 4
+    net = synth.make_prop_net(7)
+    base = dict(widths=net.widths, precision="bf16", in_mean=net.in_mean, in_std=net.in_std)
+    for kw, want in ((dict(widths=(3, 1)), L.EINVAL),                       # no hidden layer
+                     (dict(widths=(0, 1024, 1)), L.EINVAL),
+                     (dict(widths=(33, 1024, 1)), L.EINVAL),                # > 32 inputs
+                     (dict(widths=(3, 1024, 33)), L.EINVAL),                # > 32 outputs
+                     (dict(in_std=np.array([1.0, 0.0, 1.0])), L.EINVAL),
+                     (dict(out_mean=np.array([np.nan])), L.EINVAL),
+                     (dict(precision=9), L.EINVAL),
+                     (dict(precision="fp8"), L.EUNSUPPORTED),
+                     (dict(widths=(3, 1000, 512, 256, 1)), L.EUNSUPPORTED)):  # not a multiple of 256
+        args = dict(base)
+        args.update(kw)
+        d2, k2 = L.make_prop_desc(**args)
+        with pytest.raises(L.ChemDNNError) as e:
+            L.prop_workspace_bytes(d2)
+        assert e.value.status == want, kw
+    assert lib.chem_prop_eval(None, 10, 10, None, None, None) == L.EINVAL
+    assert lib.chem_prop_set_params(None, None, None) == L.EINVAL
+    assert lib.chem_prop_destroy(None) == L.EINVAL
+    d, keep = L.make_prop_desc(**base)
+    out = C.c_void_p()
+    assert lib.chem_prop_init(C.byref(d), C.c_void_p(1), None, 0, None, C.byref(out)) == L.EWORKSPACE
+    assert lib.chem_prop_workspace_bytes(C.byref(d), None) == L.EINVAL
