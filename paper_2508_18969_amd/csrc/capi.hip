@@ -43,19 +43,25 @@ struct chem_dnn {
   float hgtab[GTAB_N * 4];
 };
 
-// Property-network handle (layer-by-layer path only).
+// Property-network handle: the fused kernel's property mode for the shapes
+// it is compiled for, else the layer-by-layer path.
 struct chem_prop {
   int L, prec, widths[9];
-  int lR[8], lNQ[8];     // per layer: output row-blocks, input k-steps
+  int fused;
+  NetLayout lay;         // fused: compiled layout
+  int n_cu;
+  int lR[8], lNQ[8];     // layer by layer: output row-blocks, input k-steps
   int64_t chunk;         // cells per chunk
   uint8_t *ws;
   size_t ws_bytes;
   double *pc;            // PConst block
+  float *fc;             // FConst block (fused: operand scales 1)
   float *bias[8];
   void *wpack[8];
   uint8_t *act[2];       // activation fragment buffers of one chunk
   float *obuf;           // FP32 network output of one chunk [32][chunk]
-  double hpc[PConst::N]; // host copy kept alive for the asynchronous upload
+  double hpc[PConst::N]; // host copies kept alive for the asynchronous uploads
+  float hfc[FConst::N];
 };
 
 namespace {
@@ -242,7 +248,7 @@ int32_t pack_params(chem_dnn *h, const float *params, hipStream_t s) {
 
 StepArgs step_args(chem_dnn *h, int64_t n, int64_t ld, const double *T, const double *P,
                    const double *Y, double *Y_out, double *T_out, uint32_t *n_bad) {
-  StepArgs a;
+  StepArgs a{};
   a.T = T; a.P = P; a.Y = Y; a.Y_out = Y_out; a.T_out = T_out; a.n_bad = n_bad;
   a.n = n; a.ld = ld;
   a.ntiles = (n + h->lay.MC - 1) / h->lay.MC;
@@ -327,17 +333,35 @@ int64_t prop_chunk(const chem_prop_desc *d) {
 }
 
 struct PropPlan {
-  size_t pc, bias[8], w[8], act[2], obuf, total;
+  size_t pc, fc, bias[8], w[8], act[2], obuf, total;
   int64_t chunk;
+  bool fused;
+  NetLayout lay;
 };
 
 int32_t prop_plan(const chem_prop_desc *d, PropPlan *p) {
   int32_t st = check_prop_desc(d);
   if (st) return st;
   const int L = d->n_layers, ks = ks_of(d->precision), eb = eb_of(d->precision);
+  p->lay = NetLayout{};
+  // the fused kernel's output rows are 2 .. K+1 of 32
+  p->fused = L == 4 && d->widths[L] <= 30 &&
+             find_prop_layout(d->precision, d->widths[1], d->widths[2], d->widths[3], &p->lay);
   p->chunk = prop_chunk(d);
   size_t off = 0;
   p->pc = off; off = align_up(off + PConst::N * sizeof(double));
+  p->fc = off; off = align_up(off + FConst::N * sizeof(float));
+  if (p->fused) {
+    for (int l = 0; l < 4; ++l) {
+      p->bias[l] = off;
+      off = align_up(off + (size_t)p->lay.R[l] * 16 * sizeof(float));
+      p->w[l] = off;
+      off = align_up(off + (size_t)p->lay.R[l] * 16 * p->lay.NQ[l] * p->lay.KS * p->lay.EB);
+    }
+    p->act[0] = p->act[1] = p->obuf = 0;
+    p->total = off;
+    return CHEM_DNN_OK;
+  }
   int kmax = 32;
   for (int l = 0; l < L; ++l) {
     const int R = l == L - 1 ? 2 : d->widths[l + 1] / 16;   // output layer: 32 rows
@@ -360,6 +384,18 @@ int32_t prop_plan(const chem_prop_desc *d, PropPlan *p) {
 
 int32_t prop_pack(chem_prop *h, const float *params, hipStream_t s) {
   hipError_t e = hipSuccess;
+  if (h->fused) {
+    // the fused kernel's layout: output layer shifted by two rows
+    for (int l = 0; l < 4 && e == hipSuccess; ++l) {
+      const int N = h->widths[l + 1], K = h->widths[l], rowshift = l == 3 ? 2 : 0;
+      e = launch_pack(params + param_offset(h->widths, l, false), N, K, rowshift, h->lay.R[l],
+                      h->lay.NQ[l], h->lay.KS, h->prec, nullptr, h->wpack[l], s);
+      if (e == hipSuccess)
+        e = launch_pad_bias(params + param_offset(h->widths, l, true), N, rowshift,
+                            h->lay.R[l] * 16, h->bias[l], s);
+    }
+    return hip_status(e);
+  }
   for (int l = 0; l < h->L && e == hipSuccess; ++l) {
     const int N = h->widths[l + 1], K = h->widths[l];
     e = launch_pack(params + param_offset(h->widths, l, false), N, K, 0, h->lR[l], h->lNQ[l],
@@ -653,11 +689,14 @@ int32_t chem_prop_init(const chem_prop_desc *d, const float *params, void *works
   int dev = 0, n_cu = 0;
   st = current_device(&dev, &n_cu);
   if (st) return st;
-  if (layered_prepare() != hipSuccess) return CHEM_DNN_EHIP;
+  if ((p.fused ? p.lay.prepare() : layered_prepare()) != hipSuccess) return CHEM_DNN_EHIP;
   chem_prop *h = new (std::nothrow) chem_prop();
   if (!h) return CHEM_DNN_EHIP;
   h->L = d->n_layers;
   h->prec = d->precision;
+  h->fused = p.fused ? 1 : 0;
+  h->lay = p.lay;
+  h->n_cu = n_cu;
   for (int l = 0; l <= h->L; ++l) h->widths[l] = d->widths[l];
   const int ks = ks_of(d->precision);
   for (int l = 0; l < h->L; ++l) {
@@ -668,13 +707,21 @@ int32_t chem_prop_init(const chem_prop_desc *d, const float *params, void *works
   h->ws = (uint8_t *)workspace;
   h->ws_bytes = workspace_bytes;
   h->pc = (double *)(h->ws + p.pc);
+  h->fc = (float *)(h->ws + p.fc);
   for (int l = 0; l < h->L; ++l) {
     h->bias[l] = (float *)(h->ws + p.bias[l]);
     h->wpack[l] = h->ws + p.w[l];
   }
-  h->act[0] = h->ws + p.act[0];
-  h->act[1] = h->ws + p.act[1];
-  h->obuf = (float *)(h->ws + p.obuf);
+  if (!h->fused) {
+    h->act[0] = h->ws + p.act[0];
+    h->act[1] = h->ws + p.act[1];
+    h->obuf = (float *)(h->ws + p.obuf);
+  }
+  memset(h->hfc, 0, sizeof(h->hfc));
+  for (int l = 0; l < 4; ++l) {
+    h->hfc[FConst::ASCALE + l] = h->hfc[FConst::INV_SA + l] = 1.0f;
+    h->hfc[FConst::WSCALE + l] = h->hfc[FConst::SOUT + l] = 1.0f;
+  }
   memset(h->hpc, 0, sizeof(h->hpc));
   for (int f = 0; f < d->widths[0]; ++f) {
     h->hpc[PConst::IN_MU + f] = d->in_mean[f];
@@ -686,6 +733,8 @@ int32_t chem_prop_init(const chem_prop_desc *d, const float *params, void *works
   }
   hipStream_t s = (hipStream_t)stream;
   st = hip_status(hipMemcpyAsync(h->pc, h->hpc, sizeof(h->hpc), hipMemcpyHostToDevice, s));
+  if (st == CHEM_DNN_OK)
+    st = hip_status(hipMemcpyAsync(h->fc, h->hfc, sizeof(h->hfc), hipMemcpyHostToDevice, s));
   if (st == CHEM_DNN_OK) st = prop_pack(h, params, s);
   // the host copy must not be released before the upload finishes
   if (st == CHEM_DNN_OK && hipStreamSynchronize(s) != hipSuccess) st = CHEM_DNN_EHIP;
@@ -713,9 +762,24 @@ int32_t chem_prop_eval(chem_prop *h, int64_t n, int64_t ld, const double *x, dou
     const uintptr_t y0 = (uintptr_t)y, y1 = (uintptr_t)(y + (K - 1) * ld + n);
     if (x0 < y1 && y0 < x1) return CHEM_DNN_EINVAL;
   }
+  hipStream_t s = (hipStream_t)stream;
+  if (h->fused) {
+    StepArgs a{};
+    a.n = n;
+    a.ld = ld;
+    a.ntiles = (n + h->lay.MC - 1) / h->lay.MC;
+    for (int l = 0; l < 4; ++l) { a.w[l] = h->wpack[l]; a.b[l] = h->bias[l]; }
+    a.fc = h->fc;
+    a.dc = h->pc;
+    a.x = x;
+    a.y = y;
+    a.D = D;
+    a.K = K;
+    const int64_t grid = a.ntiles < h->n_cu ? a.ntiles : h->n_cu;
+    return hip_status(h->lay.step(a, (int)(grid < 1 ? 1 : grid), s));
+  }
   const uint8_t *end = h->ws + h->ws_bytes;
   if ((const uint8_t *)(h->obuf + 32 * h->chunk) > end) return CHEM_DNN_EWORKSPACE;
-  hipStream_t s = (hipStream_t)stream;
   hipError_t e = hipSuccess;
   for (int64_t n0 = 0; n0 < n && e == hipSuccess; n0 += h->chunk) {
     const int nc = (int)(n - n0 < h->chunk ? n - n0 : h->chunk);

@@ -50,6 +50,10 @@ struct StepArgs {
   double *omega;         // species source terms [S][ld], or NULL
   double inv_dt;         // 1 / dt of the source terms
   int S, thermo;
+  // property networks (the kernel's property mode; dc is then a PConst block)
+  const double *x;       // input fields [D][ld]
+  double *y;             // outputs [K][ld] (output k on row k + 2 of layer 4)
+  int D, K;
 };
 
 // Tabulated GELU: GTAB_N intervals of width 1/GTAB_INV_H from GTAB_LO.
@@ -131,6 +135,9 @@ struct NetLayout {
   hipError_t (*calib_tab)(const StepArgs &, int grid, hipStream_t);
   hipError_t (*prepare)();     // one-time function attributes
 };
+// The same for the kernel's property mode (hidden widths h1, h2, h3); only
+// `step` and `prepare` are set.
+bool find_prop_layout(int p, int h1, int h2, int h3, NetLayout *out);
 
 // Finds the compiled configuration for hidden widths (h1, h2, h3) in
 // precision p; returns false when this build has none.

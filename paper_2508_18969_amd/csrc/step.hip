@@ -66,8 +66,8 @@ template <class Op_, int CB_, int NW_, int H1_, int H2_, int H3_> struct Cfg {
   static constexpr int NW1 = RB1W * NQ1;             // layer-1 fragments per wave per chunk
   static constexpr int NBIAS = H1P + H2N + H3N + 32; // biases of all layers, FP32
   static constexpr int LDS_BIAS = 0;
-  static constexpr int LDS_DC = roundup(NBIAS * 4, 16);          // DConst block (FP64)
-  static constexpr int LDS_FC = LDS_DC + DConst::N * 8;          // FConst block (FP32)
+  static constexpr int LDS_DC = roundup(NBIAS * 4, 16);          // DConst or PConst block (FP64)
+  static constexpr int LDS_FC = LDS_DC + Max<DConst::N, PConst::N>::v * 8;   // FConst block (FP32)
   static constexpr int LDS_A0 = roundup(LDS_FC + FConst::N * 4, 256);
   static constexpr int LDS_A1 = LDS_A0 + NQ1 * QBYTES;
   static constexpr int LDS_A2 = LDS_A1 + 2 * QSC * QBYTES;
@@ -145,7 +145,10 @@ __device__ __forceinline__ int opaque_v(int v) {
   return v;
 }
 
-template <class C, bool CALIB, bool GT>
+// PROP: property mode - the input features are the Z-scored fields x[f]
+// (f < D) and the output rows 2 .. K+1 are scaled to y[k] = o sigma_k + mu_k;
+// dc is then a PConst block.
+template <class C, bool CALIB, bool GT, bool PROP = false>
 __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
   using Op = typename C::Op;
   using frag_t = typename C::frag_t;
@@ -186,7 +189,7 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
   // transform and thermodynamic constants too
   double *const dcl = (double *)(smem + C::LDS_DC);
   float *const fcl = (float *)(smem + C::LDS_FC);
-  for (int i = threadIdx.x; i < DConst::N; i += blockDim.x) dcl[i] = a.dc[i];
+  for (int i = threadIdx.x; i < (PROP ? PConst::N : DConst::N); i += blockDim.x) dcl[i] = a.dc[i];
   for (int i = threadIdx.x; i < FConst::N; i += blockDim.x) fcl[i] = a.fc[i];
   constexpr bool W4L = C::w4_lds(GT);
   constexpr int LW4 = C::lds_w4(GT);
@@ -213,8 +216,13 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int f = 16 * (j >> 2) + 4 * g + (j & 3);
-      const int s = f - 2 < a.S ? f - 2 : a.S - 1;
-      xin[j] = __builtin_nontemporal_load(f == 0 ? &a.T[ii] : f == 1 ? &a.P[ii] : &a.Y[(int64_t)(s > 0 ? s : 0) * a.ld + ii]);
+      if constexpr (PROP) {
+        // fields past the inputs read the last one (zeroed below)
+        xin[j] = __builtin_nontemporal_load(&a.x[(int64_t)(f < a.D ? f : a.D - 1) * a.ld + ii]);
+      } else {
+        const int s = f - 2 < a.S ? f - 2 : a.S - 1;
+        xin[j] = __builtin_nontemporal_load(f == 0 ? &a.T[ii] : f == 1 ? &a.P[ii] : &a.Y[(int64_t)(s > 0 ? s : 0) * a.ld + ii]);
+      }
     }
   };
   if (C::NW == CB || w < CB) load_xin(blockIdx.x);
@@ -243,12 +251,18 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
           // first two slots of the lanes with g == 0
           const int f = 16 * h + 4 * g + r;
           const double x = xin[4 * h + r];
-          float z = __builtin_fmaf(ypow(x, lam), fcl[FConst::ZA + f], fcl[FConst::ZC + f]);
-          z = f - 2 < a.S ? z : 0.0f;
-          if (h == 0 && r < 2) {
-            const float ztp = r == 0 ? (float)((x - dcl[DConst::T_MU]) * dcl[DConst::T_IS])
-                                     : (float)((x - dcl[DConst::P_MU]) * dcl[DConst::P_IS]);
-            z = g == 0 ? ztp : z;
+          float z;
+          if constexpr (PROP) {
+            z = (float)((x - dcl[PConst::IN_MU + f]) * dcl[PConst::IN_IS + f]);
+            z = f < a.D ? z : 0.0f;
+          } else {
+            z = __builtin_fmaf(ypow(x, lam), fcl[FConst::ZA + f], fcl[FConst::ZC + f]);
+            z = f - 2 < a.S ? z : 0.0f;
+            if (h == 0 && r < 2) {
+              const float ztp = r == 0 ? (float)((x - dcl[DConst::T_MU]) * dcl[DConst::T_IS])
+                                       : (float)((x - dcl[DConst::P_MU]) * dcl[DConst::P_IS]);
+              z = g == 0 ? ztp : z;
+            }
           }
           z = valid ? z : 0.0f;
           if (CALIB) amx[0] = umaxf(amx[0], __builtin_fabsf(z));
@@ -633,7 +647,7 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
     const bool vpost = ipost < a.n;
     const int64_t icp = vpost ? ipost : 0;
     if (C::NW == CB || w < CB) load_xin(tile + gridDim.x);
-    if (!CALIB && (C::NW == CB || w < CB)) {
+    if (!CALIB && !PROP && (C::NW == CB || w < CB)) {
       // unconditional loads from clamped, valid addresses: no branches
       Tc = __builtin_nontemporal_load(&a.T[icp]);
       Pc = __builtin_nontemporal_load(&a.P[icp]);
@@ -701,6 +715,22 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
           for (int r = 0; r < 4; ++r) o[rb][r] = __builtin_fmaf(o[rb][r], sout[3], bias[r]);
         }
 
+      if constexpr (PROP) {
+        // output k = rho - 2 of row rho = 16h + 4g + r, scaled in FP64
+        if (vpost) {
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int k = 16 * h + 4 * g + r - 2;
+              if (k >= 0 && k < a.K)
+                __builtin_nontemporal_store(
+                    __builtin_fma((double)o[h][r], dcl[PConst::OUT_SD + k], dcl[PConst::OUT_MU + k]),
+                    &a.y[(int64_t)k * a.ld + ipost]);
+            }
+        }
+        continue;
+      }
       // post: lane holds output rows rho = 16h + 4g + r, species s = rho - 2
       const int64_t i = ipost;
       const bool valid = vpost;
@@ -793,9 +823,9 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
 }
 
 // ------------------------------------------------------------------ launchers
-template <class C, bool GT>
+template <class C, bool GT, bool PROP = false>
 static hipError_t launch_step(const StepArgs &a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((chem_step_kernel<C, false, GT>), dim3(grid), dim3(C::NW * 64),
+  hipLaunchKernelGGL((chem_step_kernel<C, false, GT, PROP>), dim3(grid), dim3(C::NW * 64),
                      C::lds_bytes(GT), s, a);
   return hipGetLastError();
 }
@@ -805,18 +835,25 @@ static hipError_t launch_calib(const StepArgs &a, int grid, hipStream_t s) {
                      C::lds_bytes(GT), s, a);
   return hipGetLastError();
 }
-template <class C, bool CALIB, bool GT>
+template <class C, bool CALIB, bool GT, bool PROP = false>
 static hipError_t set_lds_limit() {
-  return hipFuncSetAttribute((const void *)chem_step_kernel<C, CALIB, GT>,
+  return hipFuncSetAttribute((const void *)chem_step_kernel<C, CALIB, GT, PROP>,
                              hipFuncAttributeMaxDynamicSharedMemorySize, C::lds_bytes(GT));
 }
 template <class C, bool WITH_CALIB>
 static hipError_t prepare() {
   hipError_t e = set_lds_limit<C, false, false>();
   if (e == hipSuccess) e = set_lds_limit<C, false, true>();
-  if (e == hipSuccess && WITH_CALIB) e = set_lds_limit<C, true, false>();
-  if (e == hipSuccess && WITH_CALIB) e = set_lds_limit<C, true, true>();
+  if constexpr (WITH_CALIB) {
+    if (e == hipSuccess) e = set_lds_limit<C, true, false>();
+    if (e == hipSuccess) e = set_lds_limit<C, true, true>();
+  }
   return e;
+}
+
+template <class C>
+static hipError_t prepare_prop() {
+  return set_lds_limit<C, false, false, true>();
 }
 
 template <class C, bool WITH_CALIB>
@@ -830,8 +867,11 @@ static void fill_layout(NetLayout *L) {
   L->lds_bytes = C::LDS_BYTES;
   L->step = launch_step<C, false>;
   L->step_tab = launch_step<C, true>;
-  L->calib = WITH_CALIB ? launch_calib<C, false> : nullptr;
-  L->calib_tab = WITH_CALIB ? launch_calib<C, true> : nullptr;
+  L->calib = L->calib_tab = nullptr;
+  if constexpr (WITH_CALIB) {      // (only then are the calibration kernels instantiated)
+    L->calib = launch_calib<C, false>;
+    L->calib_tab = launch_calib<C, true>;
+  }
   L->prepare = prepare<C, WITH_CALIB>;
 }
 
@@ -851,6 +891,34 @@ bool find_layout(int p, int h1, int h2, int h3, NetLayout *out) {
   CHEM_SHAPE(400, 200, 100)
   CHEM_SHAPE(1600, 800, 400)
 #undef CHEM_SHAPE
+  return false;
+}
+
+template <class C>
+static void fill_prop_layout(NetLayout *L) {
+  *L = NetLayout{};
+  L->KS = C::KS;
+  L->FRAG = C::FRAG;
+  L->EB = C::EB;
+  L->MC = C::MC;
+  L->R[0] = C::R1; L->R[1] = C::R2; L->R[2] = C::R3; L->R[3] = C::R4;
+  L->NQ[0] = C::NQ1; L->NQ[1] = C::NQ2; L->NQ[2] = C::NQ3; L->NQ[3] = C::NQ4;
+  L->lds_bytes = C::LDS_BYTES;
+  L->step = launch_step<C, false, true>;
+  L->prepare = prepare_prop<C>;
+}
+
+// Property mode: the density network of the supercritical flame,
+// 3-1024-512-256-1 (its 1.35 MB of BF16 weights fit the L2 of an XCD).
+bool find_prop_layout(int p, int h1, int h2, int h3, NetLayout *out) {
+  if (h1 == 1024 && h2 == 512 && h3 == 256) {
+    switch (p) {
+      case P_FP32: fill_prop_layout<Cfg<OpF32, 2, 4, 1024, 512, 256>>(out); return true;
+      case P_BF16: fill_prop_layout<Cfg<OpBF16, 4, 4, 1024, 512, 256>>(out); return true;
+      case P_FP16: fill_prop_layout<Cfg<OpF16, 4, 4, 1024, 512, 256>>(out); return true;
+      default: return false;
+    }
+  }
   return false;
 }
 

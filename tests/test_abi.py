@@ -119,21 +119,27 @@ def test_layered_shapes_workspace_and_limits(L):
 
 
 def test_property_networks_workspace_and_validation(L):
-    """The property networks (3-1024-512-256-1, 3-2048-1024-512-4): workspace
-    of the packed weights, two chunk-sized activation buffers and the FP32
-    output buffer; bad descriptions are EINVAL, shapes and formats this build
-    lacks EUNSUPPORTED; null handles are rejected."""
+    """The property networks: the density net 3-1024-512-256-1 runs in the
+    fused kernel (workspace: packed weights and constants only), the transport
+    net 3-2048-1024-512-4 and a five-layer variant of the density net layer by
+    layer (also two chunk-sized activation buffers and the FP32 output
+    buffer); bad descriptions are EINVAL, shapes and formats this build lacks
+    EUNSUPPORTED; null handles are rejected."""
     lib = L.lib()
-    for cfg, chunk_bf16 in ((7, 65536), (8, 32768)):
-        net = synth.make_prop_net(cfg)
+    for widths, chunk_bf16 in (((3, 2048, 1024, 512, 4), 32768), ((3, 1024, 512, 256, 256, 1), 65536),
+                               ((3, 1024, 512, 256, 1), 0)):
+        net = synth.make_prop_net(7, widths=widths)
         d, keep = L.make_prop_desc(net.widths, "bf16", net.in_mean, net.in_std, net.out_mean, net.out_std)
         n = L.prop_workspace_bytes(d)
         hmax = max(net.widths[1:-1])
         weights = 2 * sum(a * b for a, b in zip((32,) + net.widths[1:-1], net.widths[1:-1] + (32,)))
         assert n >= weights + 2 * hmax * chunk_bf16 * 2 + 32 * chunk_bf16 * 4
-        assert n < weights + 2 * hmax * 2 * chunk_bf16 * 2     # the chunk is not larger
+        if chunk_bf16:
+            assert n < weights + 2 * hmax * 2 * chunk_bf16 * 2     # the chunk is not larger
+        else:
+            assert n < weights + (1 << 20)                          # fused: no activation buffers
         d32, k32 = L.make_prop_desc(net.widths, "fp32", net.in_mean, net.in_std)
-        assert L.prop_workspace_bytes(d32) >= 2 * weights + 2 * hmax * 32768 * 4
+        assert L.prop_workspace_bytes(d32) >= 2 * weights + (2 * hmax * 32768 * 4 if chunk_bf16 else 0)
     net = synth.make_prop_net(7)
     base = dict(widths=net.widths, precision="bf16", in_mean=net.in_mean, in_std=net.in_std)
     for kw, want in ((dict(widths=(3, 1)), L.EINVAL),                       # no hidden layer

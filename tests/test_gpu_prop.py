@@ -1,6 +1,7 @@
 """GPU parity of the property networks (the paper's PRNet sizes,
 3-1024-512-256-1 and 3-2048-1024-512-4) through chem_prop_eval against the
-FP64 oracle (oracle/prop.py)."""
+FP64 oracle (oracle/prop.py).  The density net (workload 7) runs in the fused
+kernel's property mode, the transport net (workload 8) layer by layer."""
 import sys
 
 import numpy as np
@@ -85,15 +86,16 @@ def test_narrow_matches_emulation(cfg, prec, fmt):
     assert ge.max() <= 1.5 * ee.max()
 
 
-def test_chunks_strides_and_cell_independence():
-    """Past one chunk (65,536 cells for the density net in BF16) with a
-    ragged tail and a leading dimension above n: a cell's outputs do not
-    depend on its batch (bit for bit), and a non-finite input spoils only its
-    own cell."""
-    net = synth.make_prop_net(7)
+@pytest.mark.parametrize("cfg", [7, 8])
+def test_chunks_strides_and_cell_independence(cfg):
+    """A batch over many tiles (fused) or past two chunks of 32,768 cells
+    (layer by layer) with a ragged tail and a leading dimension above n: a
+    cell's outputs do not depend on its batch (bit for bit), and a
+    non-finite input spoils only its own cell."""
+    net = synth.make_prop_net(cfg)
     n, ld = 65536 + 1300, 65536 + 1300 + 5
-    _note(f"case prop chunks n={n} ld={ld}")
-    x = synth.make_prop_inputs(7, n)
+    _note(f"case prop chunks cfg={cfg} n={n} ld={ld}")
+    x = synth.make_prop_inputs(cfg, n)
     bad = 66000
     x[1, bad] = np.nan
     xd = torch.zeros((3, ld), dtype=torch.float64, device="cuda")
@@ -109,7 +111,7 @@ def test_chunks_strides_and_cell_independence():
     fin = np.isfinite(yc).all(axis=0)
     assert not fin[bad] and fin.sum() == n - 1
     # sampled cells against the exact oracle, within the BF16 emulation's own deviation
-    idx = synth.subsample_indices(7, n, 512)
+    idx = synth.subsample_indices(cfg, n, 512)
     idx = idx[idx != bad]
     og = _o(yc[:, idx], net)
     emu = prop.evaluate(x[:, idx], net, fmt="bf16")["o"]
