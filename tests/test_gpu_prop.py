@@ -175,3 +175,28 @@ def test_binding_rejects_aliasing_and_layouts():
     buf = torch.zeros((8, 64), dtype=torch.float64, device="cuda")
     with pytest.raises(ChemDNNError):
         h.eval(buf[:3], y=buf[2:6])                       # overlapping input and output
+
+
+@pytest.mark.parametrize("widths", [(32, 1024, 512, 256, 30), (32, 1024, 512, 256, 32), (1, 256, 256, 1)])
+def test_input_and_output_limits(widths):
+    """The largest input and output counts: 32 inputs and 30 outputs still
+    run in the fused kernel (its output rows are 2 .. 31), 32 outputs on the
+    layer-by-layer path; and the smallest net, one input and one output.
+    FP32 operands against the FP64 oracle (the FP32 bar), with random non-zero
+    biases and input statistics of a seeded draw."""
+    rng = np.random.default_rng(sum(widths))
+    n = 777
+    D, K = widths[0], widths[-1]
+    _note(f"case prop limits widths={widths} n={n}")
+    x = rng.normal(size=(D, n)) * rng.uniform(0.5, 5.0, size=(D, 1)) + rng.normal(size=(D, 1)) * 10
+    net = synth.make_prop_net(7, widths=widths, bias_scale=0.1)
+    net.in_mean, net.in_std = x.mean(axis=1), x.std(axis=1)
+    net.out_mean, net.out_std = rng.normal(size=K), rng.uniform(0.5, 2.0, size=K)
+    h = _handle(net, "fp32")
+    y = h.eval(torch.tensor(x, device="cuda"))
+    torch.cuda.synchronize()
+    ref = prop.evaluate(x, net)
+    og = _o(y.cpu().numpy(), net)
+    err = np.abs(og - ref["o"]).max(axis=0) / np.maximum(1.0, np.abs(ref["o"]).max(axis=0))
+    _note(f"  max rel err {err.max():.3e}")
+    assert err.max() <= 1e-5
