@@ -230,32 +230,42 @@ __global__ __launch_bounds__(256) void dw_kernel(GemmArgs g) {
 // GELU'(zprev)).  Workgroup tile 64 rows x 256 columns; wave w takes columns
 // 64 w .. 64 w + 63 of it as four interleaved 16-column blocks (block j holds
 // the columns 4 c + j, c = 0..15), so that every lane loads and stores four
-// consecutive columns with one 16-byte access.  The operand A (weights) is read
-// with plain loads (it is small and cached), B straight from global memory.
-// Requires B and C rows 16-byte aligned (leading dimensions multiples of 4).
+// consecutive columns with one 16-byte access.  Per 16-k step the operand A
+// (weights, 64 x 16) is loaded once by the whole workgroup with coalesced
+// loads and read from LDS (double-buffered, one barrier per step); B comes
+// straight from global memory.  The loads of step k + 1 are issued before the
+// products of step k.  Requires B and C rows 16-byte aligned (leading
+// dimensions multiples of 4).
 template <int EPI>
 __global__ __launch_bounds__(256) void fc_kernel(GemmArgs g) {
+  __shared__ __align__(16) float As[2][64][20];   // [buffer][row][k], rows padded to 80 bytes
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g4 = lane >> 4, c16 = lane & 15;
   const int64_t m0 = (int64_t)blockIdx.y * 64;
   const int64_t nc = (int64_t)blockIdx.x * 256 + 64 * w + 4 * c16;   // this lane's first column
   const bool full = nc + 3 < g.N;
-  f4 acc[4][4];
+  const bool a_kfast = g.sak == 1;
+  // element tid + 256 j of the A tile: (row, k) with the contiguous index fastest
+  auto a_row = [&](int j) { const int e = tid + 256 * j; return a_kfast ? e >> 4 : e & 63; };
+  auto a_k = [&](int j) { const int e = tid + 256 * j; return a_kfast ? e & 15 : e >> 6; };
+  float ra[4];
+  auto load_a = [&](int64_t k0) {
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) {
+      const int64_t gm = m0 + a_row(j), gk = k0 + a_k(j);
+      ra[j] = (gm < g.M && gk < g.K) ? g.A[gm * g.sam + gk * g.sak] : 0.0f;
+    }
+  };
+  auto store_a = [&](int buf) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-  for (int64_t k0 = 0; k0 < g.K; k0 += 16) {
-    float a[4][4];
-    f4 b[4];
+    for (int j = 0; j < 4; ++j) As[buf][a_row(j)][a_k(j)] = ra[j];
+  };
+  // raw B of a step: rb[e] = B[k0 + 4 g4 + e][nc .. nc + 3] (zero past K and N)
+  f4 rb[4];
+  auto load_b = [&](int64_t k0) {
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int64_t k = k0 + 4 * g4 + e;
       const bool kv = k < g.K;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int64_t m = m0 + 16 * i + c16;
-        a[i][e] = (kv && m < g.M) ? g.A[m * g.sam + k * g.sak] : 0.0f;
-      }
       const float *bp = g.B + (kv ? k : 0) * g.sbk;
       f4 v;
       if (full) {
@@ -264,14 +274,37 @@ __global__ __launch_bounds__(256) void fc_kernel(GemmArgs g) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) v[j] = nc + j < g.N ? bp[nc + j] : 0.0f;
       }
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        float x = kv ? v[j] : 0.0f;
-        if (g.gelu_b) x = gelu(x);
-        v[j] = x;
-      }
-      b[e] = v;
+      rb[e] = kv ? v : f4{0.f, 0.f, 0.f, 0.f};
     }
+  };
+  f4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+  load_a(0);
+  load_b(0);
+  store_a(0);
+  __syncthreads();
+  int buf = 0;
+  for (int64_t k0 = 0; k0 < g.K; k0 += 16) {
+    f4 b[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      b[e] = rb[e];
+      if (g.gelu_b)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) b[e][j] = gelu(b[e][j]);
+    }
+    const bool more = k0 + 16 < g.K;
+    if (more) {
+      load_a(k0 + 16);
+      load_b(k0 + 16);
+    }
+    // a[i][e] = A[m0 + 16 i + c16][k0 + 4 g4 + e]
+    f4 a[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a[i] = *(const f4 *)&As[buf][16 * i + c16][4 * g4];
 #pragma unroll
     for (int e = 0; e < 4; ++e)
 #pragma unroll
@@ -279,6 +312,10 @@ __global__ __launch_bounds__(256) void fc_kernel(GemmArgs g) {
 #pragma unroll
         for (int j = 0; j < 4; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][e], b[e][j], acc[i][j], 0, 0, 0);
+    // the other buffer was last read before the previous barrier
+    if (more) store_a(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -358,11 +395,15 @@ __global__ void mse_kernel(const float *o, int64_t ldo, const float *t, int64_t 
   if (threadIdx.x == 0) lpart[blockIdx.x] = red[0];
 }
 
+// One wave: lane l sums partials l, l + 64, ... in order, then a fixed
+// butterfly over the lanes (lane 0's order is the same on every run).
 __global__ void loss_final_kernel(const float *lpart, int nb, double denom, float *loss) {
-  if (threadIdx.x != 0) return;
+  const int l = threadIdx.x;
   double s = 0.0;
-  for (int i = 0; i < nb; ++i) s += (double)lpart[i];
-  *loss = (float)(s / denom);
+  for (int i = l; i < nb; i += 64) s += (double)lpart[i];
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
+  if (l == 0) *loss = (float)(s / denom);
 }
 
 // Normalised network input from the FP64 state, the same arithmetic as the
