@@ -15,8 +15,13 @@ namespace chemdnn {
 
 namespace {
 
+// Weight-gradient batch splits: the partials scratch holds kMaxSplit copies
+// of the largest layer; smaller layers use up to kMaxSplitAll splits of the
+// same scratch, at least kMinSplitBatch batch entries each.
 constexpr int kMaxSplit = 32;
-constexpr int kSplitChunk = 2048;
+constexpr int kMaxSplitAll = 256;
+constexpr int kMinSplitBatch = 256;
+constexpr int kSplitTarget = 1024;     // workgroups to aim for
 
 // d/dx of the tanh-form GELU with s = 0.5 (1 + tanh v) = 1/(1 + e^(-2v)):
 // GELU' = s + x * 2 s (1 - s) * sqrt(2/pi) (1 + 3 * 0.044715 x^2).
@@ -28,6 +33,21 @@ __device__ __forceinline__ float gelu_grad(float x) {
 }
 
 enum { EPI_FWD = 0, EPI_DA = 1, EPI_PART = 2 };
+
+// Workgroup ids are dealt round-robin to the 8 XCDs, each with its own L2.
+// Tile (x, y) of workgroup id in an nx x ny grid such that the ny tiles of a
+// column x run back to back on one XCD (when nx is a multiple of 8): the
+// operand panel they share is fetched into that XCD's L2 once.
+__device__ __forceinline__ void xcd_tile(int id, int nx, int ny, int &x, int &y) {
+  if (nx % 8 == 0) {
+    const int xcd = id & 7, j = id >> 3;
+    y = j % ny;
+    x = (j / ny) * 8 + xcd;
+  } else {
+    x = id % nx;
+    y = id / nx;
+  }
+}
 
 struct GemmArgs {
   const float *A, *B;
@@ -115,12 +135,18 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
 // them in turn - the same k permutation on both operands), then the four
 // partial tiles are summed in LDS in wave order.  Requires A and B rows 16-byte
 // aligned (leading dimensions multiples of 4).
-__global__ __launch_bounds__(256) void dw_kernel(GemmArgs g) {
+//
+// One-dimensional grid of tn x tm tiles x nsplit splits: the tiles of a split
+// (which read the same batch range) run back to back on one XCD.
+__global__ __launch_bounds__(256) void dw_kernel(GemmArgs g, int tn, int tm, int nsplit) {
   __shared__ float red[2][64][65];
   __shared__ float rsl[4][4][64];       // row sums of A per wave and lane group
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g4 = lane >> 4, c16 = lane & 15;
-  const int64_t m0 = (int64_t)blockIdx.y * 64, n0 = (int64_t)blockIdx.x * 64;
-  const int64_t k0 = (int64_t)blockIdx.z * g.kchunk;
+  int zt, tile;
+  xcd_tile(blockIdx.x, nsplit, tn * tm, zt, tile);
+  const int bx = tile % tn, by = tile / tn;
+  const int64_t m0 = (int64_t)by * 64, n0 = (int64_t)bx * 64;
+  const int64_t k0 = (int64_t)zt * g.kchunk;
   const int64_t k1 = (k0 + g.kchunk < g.K) ? k0 + g.kchunk : g.K;
   const int64_t ks = ((g.kchunk + 3) / 4 + 15) / 16 * 16;          // per wave, whole 16-k blocks
   const int64_t kb0 = k0 + w * ks;
@@ -181,7 +207,7 @@ __global__ __launch_bounds__(256) void dw_kernel(GemmArgs g) {
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][e], b[j][e], acc[i][j], 0, 0, 0);
   }
   // row sums: per row, the 16 (wave, lane group) partials in that order
-  if (g.bpart && blockIdx.x == 0) {
+  if (g.bpart && bx == 0) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) rsl[w][g4][16 * i + c16] = rs[i];
     __syncthreads();
@@ -189,7 +215,7 @@ __global__ __launch_bounds__(256) void dw_kernel(GemmArgs g) {
       float t = 0.0f;
       for (int ww = 0; ww < 4; ++ww)
         for (int gg = 0; gg < 4; ++gg) t += rsl[ww][gg][tid];
-      g.bpart[blockIdx.z * (int64_t)g.M + m0 + tid] = t;
+      g.bpart[zt * (int64_t)g.M + m0 + tid] = t;
     }
   }
   // the waves' partial tiles, summed in wave order ((w0 + w1) + w2) + w3,
@@ -213,7 +239,7 @@ __global__ __launch_bounds__(256) void dw_kernel(GemmArgs g) {
   __syncthreads();
   if (w >= 2) put(w - 2);
   __syncthreads();
-  float *C = g.C + blockIdx.z * g.part_stride;
+  float *C = g.C + zt * g.part_stride;
 #pragma unroll
   for (int t = 0; t < 16; ++t) {
     const int e = tid + 256 * t, mm = e >> 6, nn = e & 63;
@@ -235,13 +261,17 @@ __global__ __launch_bounds__(256) void dw_kernel(GemmArgs g) {
 // loads and read from LDS (double-buffered, one barrier per step); B comes
 // straight from global memory.  The loads of step k + 1 are issued before the
 // products of step k.  Requires B and C rows 16-byte aligned (leading
-// dimensions multiples of 4).
+// dimensions multiples of 4).  One-dimensional grid of nx column tiles x ny
+// row tiles: the row tiles of a column tile (which share its B panel) run
+// back to back on one XCD.
 template <int EPI>
-__global__ __launch_bounds__(256) void fc_kernel(GemmArgs g) {
+__global__ __launch_bounds__(256) void fc_kernel(GemmArgs g, int nx, int ny) {
   __shared__ __align__(16) float As[2][64][20];   // [buffer][row][k], rows padded to 80 bytes
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g4 = lane >> 4, c16 = lane & 15;
-  const int64_t m0 = (int64_t)blockIdx.y * 64;
-  const int64_t nc = (int64_t)blockIdx.x * 256 + 64 * w + 4 * c16;   // this lane's first column
+  int bx, by;
+  xcd_tile(blockIdx.x, nx, ny, bx, by);
+  const int64_t m0 = (int64_t)by * 64;
+  const int64_t nc = (int64_t)bx * 256 + 64 * w + 4 * c16;   // this lane's first column
   const bool full = nc + 3 < g.N;
   const bool a_kfast = g.sak == 1;
   // element tid + 256 j of the A tile: (row, k) with the contiguous index fastest
@@ -348,14 +378,30 @@ __global__ __launch_bounds__(256) void fc_kernel(GemmArgs g) {
     }
 }
 
-// out[i] = sum over z of part[z * stride + i], z in increasing order.
-__global__ void reduce_parts_kernel(const float *part, int64_t stride, int nz, int64_t n,
-                                    float *out) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  float s = 0.0f;
-  for (int z = 0; z < nz; ++z) s += part[z * stride + i];
-  out[i] = s;
+// Sums of split partials for two outputs in one launch: output o < n0 is
+// o0[o] = sum_z p0[z * s0 + o], the next n1 are o1 from p1 likewise.  A
+// workgroup takes 64 outputs; its four waves sum a quarter of the splits each,
+// in increasing z, and the four quarter sums are added in wave order.
+__global__ __launch_bounds__(256) void reduce_parts2_kernel(const float *p0, int64_t s0, int64_t n0,
+                                                            float *o0, const float *p1, int64_t s1,
+                                                            int64_t n1, float *o1, int nz) {
+  __shared__ float q[4][64];
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t o = blockIdx.x * (int64_t)64 + l;
+  const bool first = o < n0, valid = o < n0 + n1;
+  const float *p = first ? p0 + o : p1 + (valid ? o - n0 : 0);
+  const int64_t st = first ? s0 : s1;
+  const int zq = (nz + 3) / 4, z0 = w * zq, z1 = z0 + zq < nz ? z0 + zq : nz;
+  float acc = 0.0f;
+  if (valid)
+    for (int z = z0; z < z1; ++z) acc += p[z * st];
+  q[w][l] = acc;
+  __syncthreads();
+  if (w == 0 && valid) {
+    const float t = ((q[0][l] + q[1][l]) + q[2][l]) + q[3][l];
+    if (first) o0[o] = t;
+    else o1[o - n0] = t;
+  }
 }
 
 // out[m] = sum_b dz[m * ld + b]: one workgroup per row, fixed-order tree.
@@ -440,9 +486,10 @@ hipError_t gemm(int epi, const GemmArgs &g, int nsplit, hipStream_t s) {
   if ((epi == EPI_FWD || epi == EPI_DA) && nsplit == 1 && g.sbn == 1 && g.scn == 1 &&
       g.sbk % 4 == 0 && g.scm % 4 == 0 && ((uintptr_t)g.B | (uintptr_t)g.C) % 16 == 0 &&
       (!g.zprev || (uintptr_t)g.zprev % 16 == 0)) {
-    dim3 grid(blocks_for(g.N, 256), blocks_for(g.M, 64));
-    if (epi == EPI_FWD) hipLaunchKernelGGL(fc_kernel<EPI_FWD>, grid, dim3(256), 0, s, g);
-    else hipLaunchKernelGGL(fc_kernel<EPI_DA>, grid, dim3(256), 0, s, g);
+    const int nx = (int)blocks_for(g.N, 256), ny = (int)blocks_for(g.M, 64);
+    const dim3 grid((unsigned)nx * ny);
+    if (epi == EPI_FWD) hipLaunchKernelGGL(fc_kernel<EPI_FWD>, grid, dim3(256), 0, s, g, nx, ny);
+    else hipLaunchKernelGGL(fc_kernel<EPI_DA>, grid, dim3(256), 0, s, g, nx, ny);
     return hipGetLastError();
   }
   dim3 grid(blocks_for(g.N, 64), blocks_for(g.M, 64), nsplit);
@@ -460,15 +507,26 @@ size_t param_off(const int *w, int l) {
   return o;
 }
 
-int split_count(int64_t B) {
-  int64_t n = (B + kSplitChunk - 1) / kSplitChunk;
-  return (int)(n > kMaxSplit ? kMaxSplit : (n < 1 ? 1 : n));
-}
-
 int64_t max_layer_weights(const int *w) {
   int64_t m = 0;
   for (int l = 0; l < 4; ++l) m = m > (int64_t)w[l] * w[l + 1] ? m : (int64_t)w[l] * w[l + 1];
   return m;
+}
+
+// Batch splits of the weight gradient of an N x K layer: about kSplitTarget
+// workgroups of 64 x 64 tiles, at least kMinSplitBatch entries per split, the
+// partials within the scratch.  Depends on the shapes only, so results are
+// reproducible.
+int split_count(const int *w, int64_t B, int N, int K) {
+  const int64_t tiles = (int64_t)blocks_for(N, 64) * blocks_for(K, 64);
+  int64_t n = (kSplitTarget + tiles - 1) / tiles;
+  const int64_t by_batch = (B + kMinSplitBatch - 1) / kMinSplitBatch;
+  const int64_t by_space = (int64_t)kMaxSplit * max_layer_weights(w) / ((int64_t)N * K);
+  n = n < by_batch ? n : by_batch;
+  n = n < by_space ? n : by_space;
+  n = n < kMaxSplitAll ? n : kMaxSplitAll;
+  n = n >= 8 ? n / 8 * 8 : n;          // whole rounds over the 8 XCDs
+  return (int)(n < 1 ? 1 : n);
 }
 
 // Forward of the 4-layer net.  z: pre-activations [H1+H2+H3][ldz]; out [S][ldo].
@@ -507,11 +565,11 @@ hipError_t backward(const int *w, int64_t B, const float *x, int64_t ldx, const 
   int64_t zoffs[4] = {0, w[1], (int64_t)w[1] + w[2], 0};
   const float *dZ = gout;
   int64_t lddz = ldg;
-  const int nsplit = split_count(B);
-  const int64_t kchunk = ((B + nsplit - 1) / nsplit + 15) / 16 * 16;
   int pp = 0;
   for (int l = 3; l >= 0; --l) {
     const int N = w[l + 1], K = w[l];
+    const int nsplit = split_count(w, B, N, K);
+    const int64_t kchunk = ((B + nsplit - 1) / nsplit + 15) / 16 * 16;
     const float *ain = (l == 0) ? x : z + zoffs[l - 1] * ldz;
     const int64_t ldain = (l == 0) ? ldx : ldz;
     // dW_l = dZ_l a_(l-1)^T over the batch, split in fixed chunks
@@ -528,19 +586,20 @@ hipError_t backward(const int *w, int64_t B, const float *x, int64_t ldx, const 
     if (direct) {
       // weight and bias partials in one pass
       g.bpart = t->bpart;
-      dim3 grid(blocks_for(K, 64), blocks_for(N, 64), nsplit);
-      hipLaunchKernelGGL(dw_kernel, grid, dim3(256), 0, s, g);
+      const int tn = (int)blocks_for(K, 64), tm = (int)blocks_for(N, 64);
+      hipLaunchKernelGGL(dw_kernel, dim3((unsigned)(tn * tm * nsplit)), dim3(256), 0, s, g, tn, tm,
+                         nsplit);
       e = hipGetLastError();
     } else {
       e = gemm(EPI_PART, g, nsplit, s);
     }
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(reduce_parts_kernel, dim3(blocks_for((int64_t)N * K)), dim3(256), 0, s,
-                       (const float *)t->part, (int64_t)N * K, nsplit, (int64_t)N * K, gW);
-    if (direct)
-      hipLaunchKernelGGL(reduce_parts_kernel, dim3(blocks_for(N)), dim3(256), 0, s,
-                         (const float *)t->bpart, (int64_t)N, nsplit, (int64_t)N, gW + (size_t)N * K);
-    else
+    // weights and (direct path) biases in one launch
+    const int64_t nw = (int64_t)N * K, nb = direct ? N : 0;
+    hipLaunchKernelGGL(reduce_parts2_kernel, dim3(blocks_for(nw + nb, 64)), dim3(256), 0, s,
+                       (const float *)t->part, nw, nw, gW, (const float *)t->bpart, (int64_t)N, nb,
+                       gW + (size_t)N * K, nsplit);
+    if (!direct)
       hipLaunchKernelGGL(rowsum_kernel, dim3(N), dim3(256), 0, s, dZ, lddz, B, gW + (size_t)N * K);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // dZ_(l-1) = (W_l^T dZ_l) * GELU'(z_(l-1)), or grad_x for l = 0
@@ -572,7 +631,7 @@ size_t train_scratch_bytes(const int *w, int64_t cap) {
   int64_t mx = w[4];
   for (int l = 1; l < 4; ++l) mx = mx > w[l] ? mx : w[l];
   size_t f = (size_t)cap * (w[0] + H + w[4] + 2 * mx) + (size_t)kMaxSplit * max_layer_weights(w) +
-             (size_t)kMaxSplit * mx + 1024;
+             (size_t)kMaxSplitAll * mx + 1024;
   return f * sizeof(float) + 9 * 256;
 }
 
@@ -594,7 +653,7 @@ void train_scratch_layout(TrainScratch *t, uint8_t *base, const int *w, int64_t 
   t->dz[0] = take((size_t)cap * mx);
   t->dz[1] = take((size_t)cap * mx);
   t->part = take((size_t)kMaxSplit * max_layer_weights(w));
-  t->bpart = take((size_t)kMaxSplit * mx);
+  t->bpart = take((size_t)kMaxSplitAll * mx);
   t->lpart = take(1024);
   t->act = nullptr;
   t->nsplit = kMaxSplit;
