@@ -164,3 +164,11 @@ def test_property_networks_workspace_and_validation(L):
     out = C.c_void_p()
     assert lib.chem_prop_init(C.byref(d), C.c_void_p(1), None, 0, None, C.byref(out)) == L.EWORKSPACE
     assert lib.chem_prop_workspace_bytes(C.byref(d), None) == L.EINVAL
+    import torch
+    if not torch.cuda.is_available():
+        # a valid description and workspace: the missing device is reported
+        n = L.prop_workspace_bytes(d)
+        buf = (C.c_uint8 * (n + 256))()
+        addr = (C.addressof(buf) + 255) // 256 * 256
+        st = lib.chem_prop_init(C.byref(d), C.c_void_p(16), C.c_void_p(addr), n, None, C.byref(out))
+        assert st == L.ENODEV and not out.value
