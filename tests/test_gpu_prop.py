@@ -120,19 +120,20 @@ def test_chunks_strides_and_cell_independence(cfg):
 
 
 @pytest.mark.parametrize("cfg", [7, 8])
-def test_full_batch_sampled(cfg):
-    """The benchmark's batch of 2^20 cells in BF16, sampled cells against the
-    oracle with the statistical bars of the emulation test."""
+@pytest.mark.parametrize("prec,fmt", [("bf16", "bf16"), ("fp16", "f16")])
+def test_full_batch_sampled(cfg, prec, fmt):
+    """The benchmark's batch of 2^20 cells in BF16 and FP16, sampled cells
+    against the oracle with the statistical bars of the emulation test."""
     net = synth.make_prop_net(cfg)
     n = 1 << 20
-    _note(f"case prop full cfg={cfg} n={n}")
+    _note(f"case prop full cfg={cfg} {prec} n={n}")
     x = synth.make_prop_inputs(cfg, n)
-    h = _handle(net, "bf16")
+    h = _handle(net, prec)
     y = h.eval(torch.tensor(x, device="cuda"))
     torch.cuda.synchronize()
     idx = synth.subsample_indices(cfg, n, 1024)
     og = _o(y[:, torch.tensor(idx, device="cuda")].cpu().numpy(), net)
-    emu = prop.evaluate(x[:, idx], net, fmt="bf16")["o"]
+    emu = prop.evaluate(x[:, idx], net, fmt=fmt)["o"]
     ex = prop.evaluate(x[:, idx], net)["o"]
     ge, ee = np.abs(og - emu).ravel(), np.abs(emu - ex).ravel()
     _note(f"  gpu-emu rms {np.sqrt(np.mean(ge ** 2)):.2e} | emu-fp64 rms {np.sqrt(np.mean(ee ** 2)):.2e}")
@@ -142,12 +143,13 @@ def test_full_batch_sampled(cfg):
     assert ge.max() <= 1.5 * ee.max()
 
 
-def test_single_cell_empty_and_set_params():
+@pytest.mark.parametrize("cfg", [7, 8])
+def test_single_cell_empty_and_set_params(cfg):
     """n = 1 and n = 0; set_params gives the outputs of a handle built from
-    the new parameters (bit for bit)."""
-    net = synth.make_prop_net(7)
-    _note("case prop n=1, n=0, set_params")
-    x = synth.make_prop_inputs(7, 300)
+    the new parameters (bit for bit), on both paths."""
+    net = synth.make_prop_net(cfg)
+    _note(f"case prop n=1, n=0, set_params cfg={cfg}")
+    x = synth.make_prop_inputs(cfg, 300)
     h = _handle(net, "fp32")
     y1 = h.eval(torch.tensor(x[:, :1], device="cuda"))
     torch.cuda.synchronize()
