@@ -41,6 +41,17 @@ __device__ __forceinline__ void wait_vmem() {
   static_assert(N >= 0 && N < 64, "vmcnt range");
   asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
 }
+// Waits until at most PER * min(k, MAXK) vector-memory operations are in
+// flight (k >= 0 at run time; PER, MAXK compile-time).
+template <int PER, int MAXK>
+__device__ __forceinline__ void wait_vmem_upto(int k) {
+  if constexpr (MAXK <= 0) {
+    wait_vmem<0>();
+  } else {
+    if (k >= MAXK) wait_vmem<PER * MAXK>();
+    else wait_vmem_upto<PER, MAXK - 1>(k);
+  }
+}
 __device__ __forceinline__ void lds_barrier_all() {
   asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
@@ -117,11 +128,12 @@ __global__ __launch_bounds__(WR * WC * 64, 1) void layer_kernel(LayerArgs a) {
     for (int j = 0; j < WCB; ++j) acc[i][j] = b;
   }
 
-  // k-steps 0 .. STAGES - 2 in flight; k-step 0 in registers
+  // k-steps 0 .. STAGES - 2 in flight; k-step 0 in registers (the copies of
+  // the later ones may stay in flight)
   for (int q = 0; q < STAGES - 1 && q < a.NQ; ++q) issue(q, q);
   if constexpr (PERW > 0) {
-    if (a.NQ > 2) wait_vmem<PERW * (STAGES - 2)>();
-    else wait_vmem<0>();
+    const int issued = a.NQ < STAGES - 1 ? a.NQ : STAGES - 1;
+    wait_vmem_upto<PERW, STAGES - 2>(issued - 1);
   } else {
     wait_vmem<0>();
   }
@@ -135,12 +147,13 @@ __global__ __launch_bounds__(WR * WC * 64, 1) void layer_kernel(LayerArgs a) {
       const int qq = q + h;
       if (qq < a.NQ) {
         if (qq + 1 < a.NQ) {
-          // k-step qq + 1: this wave's copies (those of qq + 2 may be in
-          // flight), then every wave's; every wave has read k-step qq, so the
-          // stage of qq - 1 is free for k-step qq + 3
+          // k-step qq + 1: this wave's copies (those of qq + 2 .. qq +
+          // STAGES - 2 may be in flight), then every wave's; every wave has
+          // read k-step qq, so the stage of qq - 1 is free for k-step
+          // qq + STAGES - 1
           if constexpr (PERW > 0) {
-            if (qq + 2 < a.NQ) wait_vmem<PERW>();
-            else wait_vmem<0>();
+            const int last = qq + STAGES - 2 < a.NQ - 1 ? qq + STAGES - 2 : a.NQ - 1;
+            wait_vmem_upto<PERW, STAGES - 3>(last - (qq + 1));
           } else {
             wait_vmem<0>();
           }
