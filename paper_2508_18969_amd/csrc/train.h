@@ -13,13 +13,11 @@ struct TrainScratch {
   int64_t cap;            // max batch
   float *x;               // [D][cap] normalised inputs
   float *z;               // [H1+H2+H3][cap] pre-activations
-  float *act;             // [H1+H2+H3][cap] GELU outputs
   float *out;             // [S][cap] network output
   float *dz[2];           // [max hidden or S][cap] ping-pong gradients
-  float *part;            // [nsplit][max layer params] split-K partial sums
-  float *bpart;           // [nsplit][max layer width] bias-gradient partial sums
+  float *part;            // weight-gradient partials: 32 copies of the largest layer's weights
+  float *bpart;           // bias-gradient partials [up to 256 splits][max layer width]
   float *lpart;           // [1024] loss partial sums
-  int nsplit;
 };
 
 size_t train_scratch_bytes(const int *widths, int64_t max_batch);

@@ -655,8 +655,6 @@ void train_scratch_layout(TrainScratch *t, uint8_t *base, const int *w, int64_t 
   t->part = take((size_t)kMaxSplit * max_layer_weights(w));
   t->bpart = take((size_t)kMaxSplitAll * mx);
   t->lpart = take(1024);
-  t->act = nullptr;
-  t->nsplit = kMaxSplit;
 }
 
 hipError_t train_prepare() { return hipSuccess; }
