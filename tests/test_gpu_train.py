@@ -36,8 +36,12 @@ def _setup(B, seed=0):
     return net, x, t
 
 
-@pytest.mark.parametrize("B", [4096, 1000])
+@pytest.mark.parametrize("B", [4096, 1000, 65536])
 def test_forward_backward_match_fp64(B):
+    """Forward, every gradient tensor and grad_x against the FP64 oracle
+    (1e-4 relative per tensor), recomputed pre-activations bitwise equal to
+    saved ones; 65,536 is the benchmark's batch, whose weight gradients use
+    the per-layer batch splits of that size (32 to 256 splits)."""
     print(f"case train fwd/bwd B={B}", flush=True)
     net, x, t = _setup(B)
     h = make_handle(net, "fp32", max_batch=B)
@@ -104,6 +108,34 @@ def test_train_step_matches_fp64_and_is_reproducible():
     # gradient at rounding level may flip one step; nearly all agree closely
     d = np.abs(res[0][0] - q)
     assert np.mean(d > 1e-5) < 1e-3 and d.max() <= 6.1e-3
+
+
+def test_train_step_at_benchmark_batch():
+    """One Adam step at the benchmark's batch of 65,536 states: the loss (its
+    partial sums reduced by one wave) against the FP64 oracle's forward and
+    MSE to 1e-5, and two runs from the same parameters bitwise equal (the
+    split reductions have a fixed order)."""
+    B = 65536
+    print(f"case train_step full batch B={B}", flush=True)
+    net = synth.make_net(4)
+    st = synth.make_state(4, B)
+    tgt = 0.3 * np.random.default_rng(5).standard_normal((17, B))
+    h = make_handle(net, "fp32", max_batch=B)
+    T, P, Y = dev_state(st)
+    td = torch.tensor(tgt, dtype=torch.float32, device="cuda")
+    runs = []
+    for _ in range(2):
+        p = torch.tensor(net.flat_params(), device="cuda")
+        m, v, g = torch.zeros_like(p), torch.zeros_like(p), torch.empty_like(p)
+        loss = h.train_step(T, P, Y, td, p, g, m, v, 1, lr=1e-3)
+        torch.cuda.synchronize()
+        runs.append((float(loss.item()), p.cpu().numpy(), g.cpu().numpy()))
+    assert runs[0][0] == runs[1][0]
+    assert np.array_equal(runs[0][1], runs[1][1]) and np.array_equal(runs[0][2], runs[1][2])
+    x = chem.features(st.T, st.P, st.Y, net.in_mean, net.in_std, net.lam)
+    o_ref, _ = train.forward(x, net.flat_params().astype(np.float64), WIDTHS)
+    l_ref, _ = train.mse(o_ref, tgt.astype(np.float32).astype(np.float64))
+    assert abs(runs[0][0] - l_ref) <= 1e-5 * l_ref
 
 
 def test_autograd_function_matches_finite_differences():
