@@ -164,3 +164,34 @@ def test_set_params_repacks_every_layer(net):
     Yb, _ = hb.step(T, P, Y)
     torch.cuda.synchronize()
     assert torch.equal(Ya, Yb)
+
+
+def test_full_batch_sampled(net):
+    """The benchmark's batch (2^20 cells, 32 chunks) in BF16: 512 sampled
+    cells against the oracle with the same operand rounding, with the bars of
+    the emulation test above, and no bad cells."""
+    n = 1 << 20
+    _note(f"case layered full batch bf16 n={n}")
+    thermo = synth.make_thermo(6, 17)
+    st = synth.make_state(6, n)
+    h = make_handle(net, "bf16", thermo=thermo)
+    T, P, Y = dev_state(st)
+    nb = torch.zeros(1, dtype=torch.int32, device="cuda")
+    Yn, Tn = h.step(T, P, Y, n_bad=nb)
+    torch.cuda.synchronize()
+    assert int(nb.item()) == 0
+    idx = synth.subsample_indices(6, n, 512)
+    it = torch.tensor(idx, device="cuda")
+    Yg, Tg = Yn[:, it].cpu().numpy(), Tn[it].cpu().numpy()
+    sub = (st.T[idx], st.P[idx], st.Y[:, idx])
+    emu = chem.step(*sub, net, fmt="bf16", thermo=thermo)
+    ex = chem.step(*sub, net, thermo=thermo)
+    for got, e, x, name in ((Yg, emu["Y_new"], ex["Y_new"], "Y"), (Tg, emu["T_new"], ex["T_new"], "T")):
+        ge, ee = got - e, e - x
+        rg, re = _rel(got, e), _rel(e, x)
+        rms_g, rms_e = np.sqrt(np.mean(ge ** 2)), np.sqrt(np.mean(ee ** 2))
+        _note(f"  {name}: gpu-emu rms {rms_g:.2e} | emu-fp64 rms {rms_e:.2e}")
+        assert rms_g <= 0.6 * rms_e
+        assert np.median(rg) <= 0.6 * np.median(re)
+        assert np.quantile(rg, 0.99) <= 1.0 * np.quantile(re, 0.99)
+        assert rg.max() <= 1.5 * re.max()
