@@ -268,6 +268,31 @@ def test_source_terms_narrow_and_bad_cells():
                                rtol=1e-12, atol=1e-18)
 
 
+def test_source_terms_full_batch():
+    """The benchmark's source-term workload (2^20 cells, BF16): Y_out and
+    T_out bit-identical to chem_dnn_step's; at 1,024 sampled cells omega is
+    rho / dt times the kernel's own change (1e-12), the source terms of a
+    cell sum to zero (mass conservation of the renormalised update)."""
+    n, dt = 1 << 20, 1e-6
+    _note(f"case source terms full batch bf16 n={n}")
+    net = synth.make_net(2)
+    thermo = synth.make_thermo(2, 29)
+    W = synth.make_molar_masses(2, 29)
+    st = synth.make_state(2, n)
+    h = make_handle(net, "bf16", thermo=thermo, molar_mass=W)
+    T, P, Y = dev_state(st)
+    Yo, To, om = h.step_source(T, P, Y, dt)
+    Ys, Ts = h.step(T, P, Y)
+    torch.cuda.synchronize()
+    assert torch.equal(Yo, Ys) and torch.equal(To, Ts)
+    idx = synth.subsample_indices(2, n, 1024)
+    it = torch.tensor(idx, device="cuda")
+    omg, yo = om[:, it].cpu().numpy(), Yo[:, it].cpu().numpy()
+    rho = chem.mixture_density(st.T[idx], st.P[idx], st.Y[:, idx], W)
+    np.testing.assert_allclose(omg * dt / rho[None, :], yo - st.Y[:, idx], rtol=1e-12, atol=1e-18)
+    assert np.all(np.abs(omg.sum(axis=0)) <= 1e-12 * rho / dt)
+
+
 # ------------------------------------------------------------------ properties
 def test_cells_are_independent_and_runs_deterministic():
     _note("case independence bf16")
