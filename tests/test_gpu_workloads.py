@@ -64,6 +64,35 @@ def _sample_run(h, T, P, Y, idx_t):
     return out
 
 
+@pytest.mark.parametrize("prec,fmt", [("fp32", None), ("bf16", "bf16"), ("fp16", "f16")])
+def test_headline_2p20_sampled(prec, fmt):
+    """The benchmark's headline batch: 2^20 cells of the 29-species net in
+    one launch; 1,024 sampled cells against the exact oracle (FP32: 1e-5
+    relative on Y_new and T_new) or against the oracle with the same operand
+    rounding (BF16, FP16: the bars of the small-batch test)."""
+    n = 1 << 20
+    _note(f"case headline 2^20 {prec}")
+    net = synth.make_net(2)
+    thermo = synth.make_thermo(2, 29)
+    st = synth.make_state(2, n)
+    idx = synth.subsample_indices(2, n, 1024)
+    h = make_handle(net, prec, thermo=thermo)
+    dev = torch.device("cuda")
+    T, P, Y = (torch.tensor(a, device=dev) for a in (st.T, st.P, st.Y))
+    Yg, Tg, nbad = _sample_run(h, T, P, Y, torch.tensor(idx, device=dev))
+    assert nbad == 0
+    sub = (st.T[idx], st.P[idx], st.Y[:, idx])
+    ex = chem.step(*sub, net, thermo=thermo)
+    if fmt is None:
+        e_y = float(_rel(Yg, ex["Y_new"]).max())
+        e_t = float(_rel(Tg, ex["T_new"], floor=1.0).max())
+        _note(f"  rel err Y {e_y:.3e}  T {e_t:.3e}")
+        assert e_y <= 1e-5 and e_t <= 1e-5
+    else:
+        emu = chem.step(*sub, net, fmt=fmt, thermo=thermo)
+        _check_against_emulation(Yg, Tg, emu, ex, prec)
+
+
 def test_fp8_bimodal_2p24_sampled():
     """FP8 e4m3 over 2^24 cells with bimodal temperatures; scales from a
     separate calibration draw.  4096 sampled cells against the oracle's FP8
