@@ -195,3 +195,25 @@ def test_full_batch_sampled(net):
         assert np.median(rg) <= 0.6 * np.median(re)
         assert np.quantile(rg, 0.99) <= 1.0 * np.quantile(re, 0.99)
         assert rg.max() <= 1.5 * re.max()
+
+
+def test_largest_species_count():
+    """30 species, the most a description takes (32 inputs, output rows up to
+    31), on the layer-by-layer path: FP32 against the FP64 oracle (1e-5) with
+    the temperature update and the source terms, on a ragged batch."""
+    S, n = 30, 777
+    _note(f"case layered S={S} n={n}")
+    net = synth.make_net(6, widths=(S + 2, 256, 512, S), bias_scale=0.05)
+    thermo = synth.make_thermo(6, S)
+    W = synth.make_molar_masses(6, S)
+    st = synth.make_state(6, n, S=S)
+    h = make_handle(net, "fp32", thermo=thermo, molar_mass=W)
+    T, P, Y = dev_state(st)
+    Yn, Tn, om = h.step_source(T, P, Y, 1e-6)
+    torch.cuda.synchronize()
+    ref = chem.step(st.T, st.P, st.Y, net, thermo=thermo)
+    assert rel_err(Yn.cpu().numpy(), ref["Y_new"]) <= 1e-5
+    assert rel_err(Tn.cpu().numpy(), ref["T_new"], floor=1.0) <= 1e-5
+    rho = chem.mixture_density(st.T, st.P, st.Y, W)
+    np.testing.assert_allclose(om.cpu().numpy() * 1e-6 / rho[None, :], Yn.cpu().numpy() - st.Y,
+                               rtol=1e-12, atol=1e-18)
