@@ -339,9 +339,47 @@ def wl_train(torch, synth, ChemDNN, B=65536, steps=20):
             "ms_per_step": ms, "samples_per_s": B / (ms * 1e-3),
             "tflops_fwd_bwd": fl / (ms * 1e-3) * 1e-12}
     h.close()
+    out["torch_reference"] = _torch_train_step_ms(torch, net.widths, B, steps)
     out["config"] = {"batch": B, "widths": list(net.widths), "optimizer": "Adam lr 1e-3",
                      "targets": "seeded normal draws of the label shape"}
     return out, None
+
+
+def _torch_train_step_ms(torch, widths, B, steps):
+    """Context for the training step: the same network and step written with
+    torch.nn on the GPU (FP32 library matrix products, tanh GELU, MSE, fused
+    Adam, no TF32), normalised features given."""
+    torch.backends.cuda.matmul.allow_tf32 = False
+    layers = []
+    for i in range(len(widths) - 1):
+        layers.append(torch.nn.Linear(widths[i], widths[i + 1]))
+        if i < len(widths) - 2:
+            layers.append(torch.nn.GELU(approximate="tanh"))
+    net = torch.nn.Sequential(*layers).to("cuda").float()
+    opt = torch.optim.Adam(net.parameters(), lr=1e-3, fused=True)
+    gen = torch.Generator(device="cuda").manual_seed(18969)
+    x = torch.randn(B, widths[0], device="cuda", generator=gen)
+    t = torch.randn(B, widths[-1], device="cuda", generator=gen)
+
+    def step():
+        opt.zero_grad(set_to_none=True)
+        torch.nn.functional.mse_loss(net(x), t).backward()
+        opt.step()
+
+    for _ in range(3):
+        step()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    del net, opt, x, t
+    return {"ms_per_step": ms, "samples_per_s": B / (ms * 1e-3),
+            "what": "torch.nn eager, FP32 library products, fused Adam (context only)"}
 
 
 def wl_source(torch, synth, ChemDNN, n=1 << 20, dt=1e-6):
