@@ -169,6 +169,7 @@ def main():
     achieved = FLOP_PER_CELL * n / (kern_ms * 1e-3) * 1e-12
     traffic = stored_traffic(n)
 
+    torch_ref = _torch_reference_step_ms(torch, net, T, P, Y)
     # the headline state is no longer needed on the device
     del T, P, Y, Yo, To
     torch.cuda.empty_cache()
@@ -206,6 +207,7 @@ def main():
         "precisions": results,
         "workloads": extra,
         "cpu_baseline": cpu,
+        "torch_reference": torch_ref,
     }
     print(json.dumps(line), flush=True)
 
@@ -343,6 +345,57 @@ def wl_train(torch, synth, ChemDNN, B=65536, steps=20):
     out["config"] = {"batch": B, "widths": list(net.widths), "optimizer": "Adam lr 1e-3",
                      "targets": "seeded normal draws of the label shape"}
     return out, None
+
+
+def _time_ms(torch, f, reps=10, warm=3):
+    for _ in range(warm):
+        f()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        f()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def _torch_reference_step_ms(torch, net, T, P, Y):
+    """Context for the headline: the same chemistry update written with torch
+    on the GPU (library BF16 matrix products with FP32 bias and GELU, the
+    transforms and the update as elementwise torch operations in FP64), and
+    its network alone in pure BF16 (products with bias, GELU in BF16)."""
+    lam = net.lam
+    dev = T.device
+    mu = torch.tensor(net.in_mean, device=dev)
+    sd = torch.tensor(net.in_std, device=dev)
+    Ws = [torch.tensor(w, device=dev).to(torch.bfloat16) for w in net.W]
+    bs = [torch.tensor(b, device=dev).float() for b in net.b]
+
+    def mlp(a, fp32_epilogue):
+        for l in range(len(Ws)):
+            if fp32_epilogue:
+                h = torch.nn.functional.linear(a, Ws[l]).float() + bs[l]
+                a = torch.nn.functional.gelu(h, approximate="tanh").to(torch.bfloat16) if l < len(Ws) - 1 else h
+            else:
+                h = torch.nn.functional.linear(a, Ws[l], bs[l].to(torch.bfloat16))
+                a = torch.nn.functional.gelu(h, approximate="tanh") if l < len(Ws) - 1 else h
+        return a
+
+    def step():
+        yl = Y.clamp_min(0) ** lam
+        x = torch.cat([T[None], P[None], (yl - 1) / lam], 0)
+        z = ((x - mu[:, None]) / sd[:, None]).float().t().contiguous().to(torch.bfloat16)
+        o = mlp(z, True).t().double()
+        yh = (Y + ((yl + lam * o).clamp_min(0) ** (1 / lam) - Y)).clamp_min(0)
+        return yh / yh.sum(0, keepdim=True)
+
+    z0 = torch.zeros((T.shape[0], net.widths[0]), dtype=torch.bfloat16, device=dev)
+    out = {"step_ms": _time_ms(torch, step), "mlp_bf16_ms": _time_ms(torch, lambda: mlp(z0, False)),
+           "what": "torch on the GPU, library BF16 products (context only)"}
+    torch.cuda.empty_cache()
+    return out
 
 
 def _torch_train_step_ms(torch, widths, B, steps):
