@@ -77,8 +77,8 @@ def main():
         write_traffic(args.traffic[0], args.traffic[1], args.cells, args.copy_probe)
         return
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only; the chemistry update needs no "
-              "communication (cells are independent) - run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the chemistry update needs no communication "
+              "between GPUs (cells are independent) - run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -120,7 +120,7 @@ def main():
             h32.close()
         try:
             h = handle(prec, act_amax)
-        except Exception as e:          # a precision this build lacks
+        except Exception as e:          # a precision the library lacks
             results[prec] = {"error": str(e)}
             continue
         for _ in range(args.warmup):

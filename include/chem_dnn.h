@@ -101,7 +101,7 @@ typedef struct {
 
 /* Bytes of device workspace chem_dnn_init needs for `desc` (packed weights,
  * biases, scales, constants and, if max_batch > 0, training scratch).
- * EINVAL for a bad description, EUNSUPPORTED for a shape this build lacks. */
+ * EINVAL for a bad description, EUNSUPPORTED for a shape the library does not compile. */
 int32_t chem_dnn_workspace_bytes(const chem_dnn_desc *desc, size_t *bytes);
 
 /* Create a handle on the current HIP device.  params (device, FP32) is the
@@ -222,7 +222,7 @@ typedef struct {
 
 /* Device workspace for `desc`: packed weights, constants and the activation
  * buffers of one chunk of cells.  EINVAL for a bad description,
- * EUNSUPPORTED for a shape or precision this build lacks. */
+ * EUNSUPPORTED for a shape or precision the library does not offer. */
 int32_t chem_prop_workspace_bytes(const chem_prop_desc *desc, size_t *bytes);
 
 /* Create a handle on the current HIP device; params (device FP32, flat

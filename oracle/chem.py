@@ -29,7 +29,7 @@ def boxcox(y, lam):
     """Power (Box-Cox) transform of mass fractions, (y^lam - 1)/lam.
 
     Not described in the paper; it is the input transform of the chemistry
-    net in this build.  Non-positive y are taken as 0, so BC(0) = -1/lam.
+    net here.  Non-positive y are taken as 0, so BC(0) = -1/lam.
     """
     y = np.asarray(y, dtype=np.float64)
     yl = np.where(y > 0, np.power(np.maximum(y, 0.0), lam), 0.0)

@@ -140,7 +140,7 @@ struct NetLayout {
 bool find_prop_layout(int p, int h1, int h2, int h3, NetLayout *out);
 
 // Finds the compiled configuration for hidden widths (h1, h2, h3) in
-// precision p; returns false when this build has none.
+// precision p; returns false when the library has none.
 bool find_layout(int p, int h1, int h2, int h3, NetLayout *out);
 
 // Weight packing (kernels in step.hip).

@@ -123,7 +123,7 @@ def test_property_networks_workspace_and_validation(L):
     fused kernel (workspace: packed weights and constants only), the transport
     net 3-2048-1024-512-4 and a five-layer variant of the density net layer by
     layer (also two chunk-sized activation buffers and the FP32 output
-    buffer); bad descriptions are EINVAL, shapes and formats this build lacks
+    buffer); bad descriptions are EINVAL, shapes and formats the library lacks
     EUNSUPPORTED; null handles are rejected."""
     lib = L.lib()
     for widths, chunk_bf16 in (((3, 2048, 1024, 512, 4), 32768), ((3, 1024, 512, 256, 256, 1), 65536),
