@@ -320,13 +320,13 @@ int32_t check_prop_desc(const chem_prop_desc *d) {
 }
 
 // Cells per chunk: doubled from kChunk (up to 4 kChunk) while the widest
-// hidden activation of a chunk stays within 128 MiB, so that narrow networks
-// give the layer kernel enough cell tiles and the chunk's activations still
-// fit the last-level cache.
+// hidden activation of a chunk stays within 256 MiB, so that narrow networks
+// give the layer kernel enough cell tiles and their small kernels (input,
+// output layer, output scaling) enough cells per launch.
 int64_t prop_chunk(const chem_prop_desc *d) {
   int hmax = 1;
   for (int l = 1; l < d->n_layers; ++l) hmax = d->widths[l] > hmax ? d->widths[l] : hmax;
-  const int64_t cap = (int64_t)128 << 20;
+  const int64_t cap = (int64_t)256 << 20;
   int64_t c = kChunk;
   while (c < 4 * kChunk && 2 * c * hmax * eb_of(d->precision) <= cap) c *= 2;
   return c;

@@ -126,7 +126,7 @@ def test_property_networks_workspace_and_validation(L):
     buffer); bad descriptions are EINVAL, shapes and formats the library lacks
     EUNSUPPORTED; null handles are rejected."""
     lib = L.lib()
-    for widths, chunk_bf16 in (((3, 2048, 1024, 512, 4), 32768), ((3, 1024, 512, 256, 256, 1), 65536),
+    for widths, chunk_bf16 in (((3, 2048, 1024, 512, 4), 65536), ((3, 1024, 512, 256, 256, 1), 131072),
                                ((3, 1024, 512, 256, 1), 0)):
         net = synth.make_prop_net(7, widths=widths)
         d, keep = L.make_prop_desc(net.widths, "bf16", net.in_mean, net.in_std, net.out_mean, net.out_std)
@@ -135,7 +135,7 @@ def test_property_networks_workspace_and_validation(L):
         weights = 2 * sum(a * b for a, b in zip((32,) + net.widths[1:-1], net.widths[1:-1] + (32,)))
         assert n >= weights + 2 * hmax * chunk_bf16 * 2 + 32 * chunk_bf16 * 4
         if chunk_bf16:
-            assert n < weights + 2 * hmax * 2 * chunk_bf16 * 2     # the chunk is not larger
+            assert n < weights + 2 * hmax * 2 * chunk_bf16 * 2 + 32 * 2 * chunk_bf16 * 4   # not larger
         else:
             assert n < weights + (1 << 20)                          # fused: no activation buffers
         d32, k32 = L.make_prop_desc(net.widths, "fp32", net.in_mean, net.in_std)

@@ -88,7 +88,7 @@ def test_narrow_matches_emulation(cfg, prec, fmt):
 
 @pytest.mark.parametrize("cfg", [7, 8])
 def test_chunks_strides_and_cell_independence(cfg):
-    """A batch over many tiles (fused) or past two chunks of 32,768 cells
+    """A batch over many tiles (fused) or past a chunk of 65,536 cells
     (layer by layer) with a ragged tail and a leading dimension above n: a
     cell's outputs do not depend on its batch (bit for bit), and a
     non-finite input spoils only its own cell."""
