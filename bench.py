@@ -610,10 +610,18 @@ def cpu_baseline(st, net, thermo, sample, outputs, results, sampled=None, extra=
             extra[wl][prec]["max_abs_dT_K"] = float(np.max(np.abs(val[1] - refw["T_new"])))
             extra[wl][prec]["error_sample_cells"] = int(len(Tw))
     threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    # the same oracle on one thread, on the first 1024 cells of the sample
+    from threadpoolctl import threadpool_limits
+    i1 = idx[:1024]
+    with threadpool_limits(limits=1):
+        t1 = time.perf_counter()
+        chem.step(st.T[i1], st.P[i1], st.Y[:, i1], net, thermo=thermo)
+        one = len(i1) / (time.perf_counter() - t1)
     return {"value": reps * len(idx) / el, "unit": "cells/s", "cores": int(threads),
             "kind": "oracle",
             "sample": f"{len(idx)} seeded cells of the same workload, FP64 numpy oracle "
-                      f"(BLAS matmul), {reps} repetitions in {el:.1f} s"}
+                      f"(BLAS matmul), {reps} repetitions in {el:.1f} s",
+            "single_thread_value": one}
 
 
 if __name__ == "__main__":
