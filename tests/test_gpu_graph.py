@@ -99,3 +99,37 @@ def test_prop_graph_replays_equal_eager(cfg):
     for r, rep in enumerate(got):
         assert torch.equal(eager[0], rep[0]), (cfg, r)
     assert torch.isfinite(eager[0]).all()
+
+
+def test_handles_on_concurrent_streams():
+    """Two handles (the fused chemistry step and the layer-by-layer property
+    network) enqueued on two streams at once give the results they give one
+    after the other (bit for bit): each handle's state is its own workspace."""
+    from paper_2508_18969_amd import PropNet
+    _note("case concurrent streams")
+    net = synth.make_net(2)
+    thermo = synth.make_thermo(2, 29)
+    st = synth.make_state(2, 65536 + 3)
+    h = make_handle(net, "bf16", thermo=thermo)
+    T, P, Y = dev_state(st)
+    pnet = synth.make_prop_net(8)
+    x = torch.tensor(synth.make_prop_inputs(8, 70000), device="cuda")
+    hp = PropNet(pnet.widths, "bf16", torch.tensor(pnet.flat_params(), device="cuda"), pnet.in_mean,
+                 pnet.in_std, pnet.out_mean, pnet.out_std)
+    Yo, To = torch.empty_like(Y), torch.empty_like(T)
+    y = torch.empty((4, 70000), dtype=torch.float64, device="cuda")
+    h.step(T, P, Y, Y_out=Yo, T_out=To)
+    hp.eval(x, y)
+    torch.cuda.synchronize()
+    ref = [Yo.clone(), To.clone(), y.clone()]
+    for o in (Yo, To, y):
+        o.fill_(-1.0)
+    torch.cuda.synchronize()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    for _ in range(3):
+        with torch.cuda.stream(s1):
+            h.step(T, P, Y, Y_out=Yo, T_out=To)
+        with torch.cuda.stream(s2):
+            hp.eval(x, y)
+    torch.cuda.synchronize()
+    assert torch.equal(Yo, ref[0]) and torch.equal(To, ref[1]) and torch.equal(y, ref[2])
