@@ -275,7 +275,9 @@ __global__ __launch_bounds__(256) void prop_prep_kernel(PropPrepArgs a) {
 }
 
 // ------------------------------------------------------------------ post
-// Thread per cell: steps 4-7 from the FP32 network output O[s][cell].
+// Thread per cell: steps 4-7 from the FP32 network output O[s][cell].  The
+// species loops are unrolled to the 30-species maximum (guarded by S), so
+// the updated fractions stay in registers between the passes.
 __global__ __launch_bounds__(256) void post_kernel(PostArgs a) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= a.nc) return;
@@ -283,30 +285,32 @@ __global__ __launch_bounds__(256) void post_kernel(PostArgs a) {
   const float lam = a.fc[FConst::LAM], inv_lam = a.fc[FConst::INV_LAM];
   const double T = a.T[i], P = a.P[i], t_ref = a.dc[DConst::T_REF];
   bool bad = !__builtin_isfinite(T) || !__builtin_isfinite(P);
+  constexpr int SMAX = 30;
+  double y[SMAX], yh[SMAX];
   double ssum = 0.0, h0 = 0.0, ry = 0.0;
-  for (int s = 0; s < a.S; ++s) {
+#pragma unroll
+  for (int s = 0; s < SMAX; ++s) {
+    y[s] = 0.0;
+    yh[s] = 0.0;
+    if (s >= a.S) continue;
     const int rho = s + 2;
-    const double y = a.Y[(int64_t)s * a.ld + i];
-    bad |= !__builtin_isfinite(y);
+    y[s] = a.Y[(int64_t)s * a.ld + i];
+    bad |= !__builtin_isfinite(y[s]);
     const float o = a.O[(size_t)s * a.ldo + c];
-    double yh = y + inv_change(y, __builtin_fmaf(o, a.fc[FConst::PA + rho], a.fc[FConst::PB + rho]),
-                               lam, inv_lam);
-    yh = yh > 0.0 ? yh : 0.0;
-    ssum += yh;
-    h0 += y * (a.dc[DConst::HF + rho] + a.dc[DConst::CP + rho] * (T - t_ref));
-    ry += y * a.dc[DConst::WINV + rho];
+    const double v = y[s] + inv_change(y[s], __builtin_fmaf(o, a.fc[FConst::PA + rho], a.fc[FConst::PB + rho]),
+                                       lam, inv_lam);
+    yh[s] = v > 0.0 ? v : 0.0;
+    ssum += yh[s];
+    h0 += y[s] * (a.dc[DConst::HF + rho] + a.dc[DConst::CP + rho] * (T - t_ref));
+    ry += y[s] * a.dc[DConst::WINV + rho];
   }
   const double rsum = 1.0 / ssum;
   double hn = 0.0, cn = 0.0;
   bool nonfin = false;
-  for (int s = 0; s < a.S; ++s) {
-    const double y = a.Y[(int64_t)s * a.ld + i];
-    const float o = a.O[(size_t)s * a.ldo + c];
-    // recomputed instead of kept: the species loop stays in registers
-    double yh = y + inv_change(y, __builtin_fmaf(o, a.fc[FConst::PA + s + 2], a.fc[FConst::PB + s + 2]),
-                               lam, inv_lam);
-    yh = yh > 0.0 ? yh : 0.0;
-    const double yn = yh * rsum;
+#pragma unroll
+  for (int s = 0; s < SMAX; ++s) {
+    if (s >= a.S) continue;
+    const double yn = yh[s] * rsum;
     nonfin |= !__builtin_isfinite(yn);
     hn += yn * a.dc[DConst::HF + s + 2];
     cn += yn * a.dc[DConst::CP + s + 2];
@@ -314,17 +318,12 @@ __global__ __launch_bounds__(256) void post_kernel(PostArgs a) {
   const double Tn = a.thermo ? t_ref + (h0 - hn) / cn : T;
   const bool okc = !bad && !nonfin && ssum > 0.0 && __builtin_isfinite(ssum) && __builtin_isfinite(Tn);
   const double rho_dt = a.omega && okc ? P / (kRGas * T * ry) * a.inv_dt : 0.0;
-  for (int s = 0; s < a.S; ++s) {
-    const double y = a.Y[(int64_t)s * a.ld + i];
-    double yn = y;
-    if (okc) {
-      const float o = a.O[(size_t)s * a.ldo + c];
-      double yh = y + inv_change(y, __builtin_fmaf(o, a.fc[FConst::PA + s + 2], a.fc[FConst::PB + s + 2]),
-                                 lam, inv_lam);
-      yn = (yh > 0.0 ? yh : 0.0) * rsum;
-    }
+#pragma unroll
+  for (int s = 0; s < SMAX; ++s) {
+    if (s >= a.S) continue;
+    const double yn = okc ? yh[s] * rsum : y[s];
     a.Y_out[(int64_t)s * a.ld + i] = yn;
-    if (a.omega) a.omega[(int64_t)s * a.ld + i] = okc ? rho_dt * (yn - y) : 0.0;
+    if (a.omega) a.omega[(int64_t)s * a.ld + i] = okc ? rho_dt * (yn - y[s]) : 0.0;
   }
   if (a.T_out) a.T_out[i] = okc ? Tn : T;
   if (!okc && a.n_bad) atomicAdd(a.n_bad, 1u);
