@@ -88,6 +88,18 @@ def gelu_table(x, coeffs=None):
     return np.where(x < GELU_TAB_LO, 0.0, np.where(x > GELU_TAB_HI, x, y))
 
 
+def gelu_table16_coeffs():
+    """The same coefficients rounded once to FP16 (round to nearest even):
+    the paper implements both FP32- and FP16-precision tabulation of the
+    GELU (Sec. 3.3.2)."""
+    return round_to(gelu_table_coeffs(), "f16")
+
+
+def gelu_table16(x):
+    """The tabulated GELU with FP16 coefficients, evaluated exactly (FP64)."""
+    return gelu_table(x, gelu_table16_coeffs())
+
+
 def gelu_grad(x):
     """d/dx of the tanh-form GELU."""
     x = np.asarray(x, dtype=np.float64)

@@ -301,6 +301,29 @@ def test_gelu_table_outside_and_jump():
     assert abs(jump - abs(chem.gelu(-3.0))) <= 1e-6
 
 
+def test_gelu_table16_coefficients_and_error():
+    """FP16 tabulation (Sec. 3.3.2): the coefficients are the FP32 table's
+    FP64 values rounded once to FP16 - numpy's own FP16 conversion (round to
+    nearest even) gives the same values; against the FP64 table the error is
+    at most the coefficient rounding, |dc0| + |dc1| h/2 + |dc2| (h/2)^2 with
+    each |dc_k| <= 2^-11 |c_k|; against the tanh form that plus the table's
+    own Taylor error (<= 1.6e-8)."""
+    c64 = chem.gelu_table_coeffs()
+    c16 = chem.gelu_table16_coeffs()
+    np.testing.assert_array_equal(c16, c64.astype(np.float16).astype(np.float64))
+    dc = np.abs(c16 - c64)
+    assert np.all(dc <= 2.0 ** -11 * np.abs(c64))
+    x = np.linspace(-3.0, 3.0, 600001)
+    i = np.clip(np.floor((x + 3.0) / 0.01), 0, 599).astype(int)
+    d = np.abs(x - (-3.0 + (i + 0.5) * 0.01))
+    bound = dc[i, 0] + dc[i, 1] * d + dc[i, 2] * d * d
+    e16 = np.abs(chem.gelu_table16(x) - chem.gelu_table(x))
+    assert np.all(e16 <= bound * (1 + 1e-9) + 1e-15)
+    err = np.max(np.abs(chem.gelu_table16(x) - chem.gelu(x)))
+    assert err <= np.max(bound) + 1.6e-8
+    assert 1e-4 <= err <= 1.6e-3          # FP16's 11 bits on values up to 3
+
+
 # ------------------------------------------------------------------ source terms
 def test_density_of_a_single_species_is_the_ideal_gas_law():
     """One species: rho = P W / (R T); nitrogen at 300 K and 1 atm is
