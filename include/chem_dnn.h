@@ -64,11 +64,16 @@ enum {
 
 enum {
     CHEM_DNN_GELU_TANH = 0,   /* 0.5x(1 + tanh(sqrt(2/pi)(x + 0.044715x^3))) evaluated in FP32 */
-    CHEM_DNN_GELU_TABLE = 1   /* the tabulated GELU of Sec. 3.3.2: 0 for x < -3, x for x > 3, and
+    CHEM_DNN_GELU_TABLE = 1,  /* the tabulated GELU of Sec. 3.3.2: 0 for x < -3, x for x > 3, and
                                  on [-3, 3] 600 intervals of 0.01, each the second-order Taylor
                                  expansion about its midpoint (error <= 1.7e-8 inside, a jump of
                                  |GELU(-+3)| = 3.6e-3 at the ends); inference only - training
                                  always uses the tanh form */
+    CHEM_DNN_GELU_TABLE16 = 2 /* the same table with its coefficients rounded to FP16 (the
+                                 paper implements FP32- and FP16-precision tabulation,
+                                 Sec. 3.3.2): 4.8 KB instead of 9.6 KB; evaluated in FP32;
+                                 error against the tanh form up to 1.5e-3 (coefficient
+                                 rounding) */
 };
 
 /* Network and transform description.  All pointers are host pointers; the
@@ -97,6 +102,11 @@ typedef struct {
     int64_t max_batch;          /* largest batch of chem_dnn_train_step (0 = no training) */
     const double *molar_mass;   /* [S] species molar masses kg/mol, > 0; NULL -> no source
                                    terms (chem_dnn_step_source returns EINVAL) */
+    int64_t recompute_chunk;    /* training memory: 0 = the workspace holds the activations of
+                                   max_batch samples; > 0 (a multiple of 16) = of this many
+                                   samples only: training runs chunk by chunk and pre-activations
+                                   that were not saved are recomputed per chunk, so the
+                                   workspace no longer grows with the batch */
 } chem_dnn_desc;
 
 /* Bytes of device workspace chem_dnn_init needs for `desc` (packed weights,
@@ -152,6 +162,18 @@ int32_t chem_dnn_calibrate(chem_dnn *h, int64_t n, int64_t ld, const double *T,
  * for FP8, 1 otherwise.  Synchronises the handle's stream. */
 int32_t chem_dnn_get_scales(chem_dnn *h, float *act_scale, float *w_scale, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Training.  The paper's solver infers a pre-trained network (Sec. 2,
+ * DeepFlame paragraph: the chemical source terms come from inferencing the
+ * pre-trained ODENet); it does not describe how the network is trained.  The
+ * entry points below are this library's own differentiable path for
+ * training or fine-tuning the chemistry network on labels from a stiff
+ * integrator: an FP32 forward that saves (or recomputes) the hidden
+ * pre-activations, an MSE loss on the normalised Box-Cox increment, a
+ * hand-written backward of the tanh-form GELU network and Adam (Kingma & Ba,
+ * Algorithm 1).  Fused network shapes only.
+ * ------------------------------------------------------------------------ */
+
 /* Plain MLP forward in FP32 on feature-major batches (training path):
  *   x     device FP32 [D][ld]  normalised inputs, D = widths[0]
  *   out   device FP32 [S][ld]  linear output
@@ -164,10 +186,13 @@ int32_t chem_dnn_mlp_forward(chem_dnn *h, int64_t B, int64_t ld, const float *x,
 /* Backward of chem_dnn_mlp_forward for dL/d out = grad_out (device FP32
  * [S][ld]); needs B <= max_batch (gradient scratch).  saved: the
  * pre-activations of the forward with the same x and params, or NULL to
- * recompute them from x (activation recomputation).  grad_params
- * (device FP32, flat like params) is overwritten; grad_x (device FP32 [D][ld])
- * is written when not NULL.  The batch reduction has a fixed order: results are
- * bitwise reproducible. */
+ * recompute them from x (activation recomputation).  The batch is processed
+ * in chunks of the handle's recompute_chunk samples (one chunk without it):
+ * per chunk the pre-activations are copied from `saved` or recomputed, and the
+ * gradients of later chunks are added in chunk order.  grad_params (device
+ * FP32, flat like params) is overwritten; grad_x (device FP32 [D][ld]) is
+ * written when not NULL.  The batch reduction has a fixed order: results are
+ * bitwise reproducible, and equal with and without `saved`. */
 int32_t chem_dnn_mlp_backward(chem_dnn *h, int64_t B, int64_t ld, const float *x,
                               const float *params, const float *saved, const float *grad_out,
                               float *grad_params, float *grad_x, void *stream);
@@ -180,8 +205,12 @@ int32_t chem_dnn_mlp_backward(chem_dnn *h, int64_t B, int64_t ld, const float *x
  * (device FP32, flat, updated in place).  grads (device FP32, flat) receives
  * the gradient; *loss (device FP32) the loss before the update.  The handle's
  * packed inference weights are NOT refreshed; call chem_dnn_set_params.
- * recompute != 0 keeps only the inputs and recomputes pre-activations in the
- * backward. */
+ * Memory: with recompute_chunk > 0 in the description the step runs chunk by
+ * chunk (features, forward, loss gradient and backward of one chunk, its
+ * weight and bias gradients added to those of the earlier chunks in order),
+ * so only one chunk's activations exist at a time - nothing needs recomputing,
+ * since a sample's loss gradient does not depend on the other samples.
+ * recompute: kept for compatibility; the schedule follows the description. */
 int32_t chem_dnn_train_step(chem_dnn *h, int64_t B, int64_t ld, const double *T,
                             const double *P, const double *Y, const float *target,
                             float *params, float *grads, float *adam_m, float *adam_v,
@@ -190,6 +219,31 @@ int32_t chem_dnn_train_step(chem_dnn *h, int64_t B, int64_t ld, const double *T,
 
 /* Release the handle (host memory only; the caller frees the workspace). */
 int32_t chem_dnn_destroy(chem_dnn *h);
+
+/* Layer dump, for testing the kernels layer by layer (the products of one
+ * layer against an exact recomputation from the very operands the matrix
+ * cores received, and each activation against its accumulators).  Runs the
+ * network of chem_dnn_step on n <= CHEM_DNN_DEBUG_MAX_CELLS cells with the
+ * same kernels, operand formats and schedules, and instead of the update
+ * writes, for every layer l = 0 .. L-1:
+ *   qin  device FP32 [sum_l widths[l]][n]; rows in_row(l) = sum_{k<l} widths[k]
+ *        onward: layer l's input as the operand values fed to the matrix
+ *        cores (quantised to the handle's precision; for FP8 the scaled
+ *        values a / act_scale[l]), decoded exactly to FP32.  Layer 0's input
+ *        is the Z-scored network input.
+ *   acc  device FP32 [sum_l widths[l+1]][n]; rows acc_row(l) =
+ *        sum_{k<l} widths[k+1] onward: layer l's FP32 accumulators after all
+ *        its products, before the activation.  For FP32, BF16 and FP16 they
+ *        started at the bias; for FP8 at 0, and the result is scaled by
+ *        act_scale[l] * w_scale[l] and given the bias afterwards.  For the
+ *        output layer, rows are species.
+ * Tanh-form GELU handles only (EUNSUPPORTED otherwise).  Y_out/T_out are not
+ * touched.  The dump is the kernels' own debug build of the same code, not
+ * a separate implementation. */
+#define CHEM_DNN_DEBUG_MAX_CELLS 4096
+int32_t chem_dnn_debug_layers(chem_dnn *h, int64_t n, int64_t ld, const double *T,
+                              const double *P, const double *Y, float *qin, float *acc,
+                              void *stream);
 
 /* ------------------------------------------------------------------------
  * Property networks.  For flames at supercritical pressure a second network
@@ -249,9 +303,9 @@ int32_t chem_prop_destroy(chem_prop *h);
 /* Static description of a status code. */
 const char *chem_dnn_strerror(int32_t status);
 
-/* ABI version of this header: 4 (2 added gelu_form to chem_dnn_desc; 3 added
+/* ABI version of this header: 5 (2 added gelu_form to chem_dnn_desc; 3 added
  * molar_mass at its end and chem_dnn_step_source; 4 added the property
- * networks, chem_prop_*). */
+ * networks, chem_prop_*; 5 added chem_dnn_debug_layers). */
 int32_t chem_dnn_abi_version(void);
 
 #ifdef __cplusplus

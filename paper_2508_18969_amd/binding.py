@@ -23,7 +23,9 @@ EXPORTS = ("chem_dnn_workspace_bytes", "chem_dnn_init", "chem_dnn_set_params", "
            "chem_dnn_step_source", "chem_dnn_calibrate", "chem_dnn_get_scales", "chem_dnn_mlp_forward",
            "chem_dnn_mlp_backward", "chem_dnn_train_step", "chem_dnn_destroy",
            "chem_dnn_strerror", "chem_dnn_abi_version", "chem_prop_workspace_bytes",
-           "chem_prop_init", "chem_prop_set_params", "chem_prop_eval", "chem_prop_destroy")
+           "chem_prop_init", "chem_prop_set_params", "chem_prop_eval", "chem_prop_destroy",
+           "chem_dnn_debug_layers")
+DEBUG_MAX_CELLS = 4096
 
 _dp = C.POINTER(C.c_double)
 _fp = C.POINTER(C.c_float)
@@ -34,7 +36,7 @@ class Desc(C.Structure):
                 ("precision", C.c_int32), ("gelu_form", C.c_int32), ("boxcox_lambda", C.c_double),
                 ("in_mean", _dp), ("in_std", _dp), ("out_mean", _dp), ("out_std", _dp),
                 ("act_amax", _fp), ("thermo_hf", _dp), ("thermo_cp", _dp), ("t_ref", C.c_double),
-                ("max_batch", C.c_int64), ("molar_mass", _dp)]
+                ("max_batch", C.c_int64), ("molar_mass", _dp), ("recompute_chunk", C.c_int64)]
 
 
 class PropDesc(C.Structure):
@@ -73,6 +75,7 @@ def lib():
         L.chem_dnn_train_step.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp, i64,
                                           C.c_float, C.c_int32, vp, vp]
         L.chem_dnn_destroy.argtypes = [vp]
+        L.chem_dnn_debug_layers.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp]
         L.chem_prop_workspace_bytes.argtypes = [C.POINTER(PropDesc), C.POINTER(C.c_size_t)]
         L.chem_prop_init.argtypes = [C.POINTER(PropDesc), vp, vp, C.c_size_t, vp, C.POINTER(vp)]
         L.chem_prop_set_params.argtypes = [vp, vp, vp]
@@ -125,6 +128,38 @@ def _check_field(t, name, rows, n, ld, dtype):
         raise ValueError(f"{name}: leading dimension {t.stride(0)}, expected {ld} (that of the state)")
 
 
+def _check_counter(t, name="n_bad"):
+    """The bad-cell counter: a CUDA 32-bit integer tensor with at least one
+    element (the kernels add to its first element with a device atomic)."""
+    import torch
+    if t is None:
+        return
+    if (not isinstance(t, torch.Tensor) or not t.is_cuda
+            or t.dtype not in (torch.int32, torch.uint32) or t.numel() < 1):
+        raise ValueError(f"{name}: expected a CUDA int32 tensor with at least one element")
+
+
+def _check_params(t, count, name="params"):
+    """A flat FP32 parameter vector on the device, contiguous, `count` long."""
+    import torch
+    if (not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32
+            or not t.is_contiguous() or t.numel() != count):
+        raise ValueError(f"{name}: expected a contiguous CUDA float32 tensor of {count} elements")
+
+
+def n_params(widths):
+    return sum(int(widths[i]) * int(widths[i + 1]) + int(widths[i + 1])
+               for i in range(len(widths) - 1))
+
+
+def _check_saved(t, rows, B, ld):
+    """Saved pre-activations of the training forward: CUDA float32 [rows][B]
+    with the batch index fastest and leading dimension ld (that of x)."""
+    if t is None:
+        return
+    _check_field(t, "saved", rows, B, ld, __import__("torch").float32)
+
+
 def _stream():
     import torch
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
@@ -137,11 +172,11 @@ def _arr(a, ctype):
     return a, a.ctypes.data_as(C.POINTER(ctype))
 
 
-GELU_FORMS = {"tanh": 0, "table": 1}
+GELU_FORMS = {"tanh": 0, "table": 1, "table16": 2}
 
 
 def make_desc(widths, precision, in_mean, in_std, out_mean=None, out_std=None, act_amax=None,
-              thermo=None, max_batch=0, lam=0.1, gelu="tanh", molar_mass=None):
+              thermo=None, max_batch=0, lam=0.1, gelu="tanh", molar_mass=None, recompute_chunk=0):
     """Fills a Desc; returns (desc, keepalive) - keep the second alive while the
     desc is in use."""
     d = Desc()
@@ -167,6 +202,7 @@ def make_desc(widths, precision, in_mean, in_std, out_mean=None, out_std=None, a
         keep += [a, b]
         d.thermo_hf, d.thermo_cp, d.t_ref = p, q, float(tref)
     d.max_batch = int(max_batch)
+    d.recompute_chunk = int(recompute_chunk)
     if molar_mass is not None:
         a, p = _arr(molar_mass, C.c_double)
         keep.append(a)
@@ -188,7 +224,8 @@ class ChemDNN:
     """
 
     def __init__(self, widths, precision, params, in_mean, in_std, out_mean=None, out_std=None,
-                 act_amax=None, thermo=None, max_batch=0, lam=0.1, gelu="tanh", molar_mass=None):
+                 act_amax=None, thermo=None, max_batch=0, lam=0.1, gelu="tanh", molar_mass=None,
+                 recompute_chunk=0):
         import torch
         self.widths = tuple(int(w) for w in widths)
         self.S = self.widths[-1]
@@ -196,7 +233,8 @@ class ChemDNN:
         self.precision = precision
         self.thermo = thermo is not None
         desc, keep = make_desc(self.widths, precision, in_mean, in_std, out_mean, out_std,
-                               act_amax, thermo, max_batch, lam, gelu, molar_mass)
+                               act_amax, thermo, max_batch, lam, gelu, molar_mass, recompute_chunk)
+        _check_params(params, n_params(self.widths))
         nbytes = workspace_bytes(desc)
         dev = params.device
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
@@ -224,6 +262,7 @@ class ChemDNN:
         for t, nm, r in ((T, "T", 1), (P, "P", 1), (Y, "Y", self.S), (Y_out, "Y_out", self.S),
                          (T_out, "T_out", 1)):
             _check_field(t, nm, r, n, ld, f64)
+        _check_counter(n_bad)
         _check(lib().chem_dnn_step(self._h, n, ld, _ptr(T), _ptr(P), _ptr(Y), _ptr(Y_out),
                                    _ptr(T_out), _ptr(n_bad), _stream()), "chem_dnn_step")
         return Y_out, T_out
@@ -244,6 +283,7 @@ class ChemDNN:
         for t, nm, r in ((T, "T", 1), (P, "P", 1), (Y, "Y", self.S), (Y_out, "Y_out", self.S),
                          (T_out, "T_out", 1), (omega, "omega", self.S)):
             _check_field(t, nm, r, n, ld, f64)
+        _check_counter(n_bad)
         _check(lib().chem_dnn_step_source(self._h, n, ld, _ptr(T), _ptr(P), _ptr(Y), _ptr(Y_out),
                                           _ptr(T_out), _ptr(omega), float(dt), _ptr(n_bad),
                                           _stream()), "chem_dnn_step_source")
@@ -261,6 +301,32 @@ class ChemDNN:
                                         _stream()), "chem_dnn_calibrate")
         return amax
 
+    def debug_layers(self, T, P, Y):
+        """Layer dump of chem_dnn_debug_layers for n <= DEBUG_MAX_CELLS cells:
+        (qin, acc), lists over the layers of CUDA float32 tensors [widths[l]][n]
+        (the input operand values of layer l as the matrix cores received
+        them) and [widths[l+1]][n] (its FP32 accumulators before the
+        activation)."""
+        import torch
+        n = int(T.shape[0])
+        ld = int(Y.stride(0)) if Y.dim() == 2 and self.S > 1 else n
+        for t, nm, r in ((T, "T", 1), (P, "P", 1), (Y, "Y", self.S)):
+            _check_field(t, nm, r, n, ld, torch.float64)
+        if n > DEBUG_MAX_CELLS:
+            raise ValueError(f"debug_layers: at most {DEBUG_MAX_CELLS} cells")
+        w = self.widths
+        qin = torch.full((sum(w[:-1]), n), float("nan"), dtype=torch.float32, device=T.device)
+        acc = torch.full((sum(w[1:]), n), float("nan"), dtype=torch.float32, device=T.device)
+        _check(lib().chem_dnn_debug_layers(self._h, n, ld, _ptr(T), _ptr(P), _ptr(Y), _ptr(qin),
+                                           _ptr(acc), _stream()), "chem_dnn_debug_layers")
+        qs, accs, ri, ra = [], [], 0, 0
+        for l in range(self.L):
+            qs.append(qin[ri:ri + w[l]])
+            accs.append(acc[ra:ra + w[l + 1]])
+            ri += w[l]
+            ra += w[l + 1]
+        return qs, accs
+
     def scales(self):
         a = (C.c_float * self.L)()
         w = (C.c_float * self.L)()
@@ -268,6 +334,7 @@ class ChemDNN:
         return np.array(a[:]), np.array(w[:])
 
     def set_params(self, params):
+        _check_params(params, n_params(self.widths))
         _check(lib().chem_dnn_set_params(self._h, _ptr(params), _stream()), "chem_dnn_set_params")
 
     # -- training ---------------------------------------------------------
@@ -276,6 +343,8 @@ class ChemDNN:
         B = int(x.shape[1])
         ld = int(x.stride(0))
         _check_field(x, "x", self.widths[0], B, ld, torch.float32)
+        _check_saved(saved, hidden_total(self.widths), B, ld)
+        _check_params(params, n_params(self.widths))
         out = torch.empty((self.S, B), dtype=torch.float32, device=x.device)
         if out.stride(0) != ld:
             out = torch.empty((self.S, ld), dtype=torch.float32, device=x.device)[:, :B]
@@ -289,6 +358,8 @@ class ChemDNN:
         ld = int(x.stride(0))
         _check_field(x, "x", self.widths[0], B, ld, torch.float32)
         _check_field(grad_out, "grad_out", self.S, B, ld, torch.float32)
+        _check_saved(saved, hidden_total(self.widths), B, ld)
+        _check_params(params, n_params(self.widths))
         gp = torch.empty_like(params)
         gx = torch.empty((x.shape[0], ld), dtype=torch.float32, device=x.device)[:, :B] \
             if want_grad_x else None
@@ -305,11 +376,14 @@ class ChemDNN:
         for t, nm, r in ((T, "T", 1), (P, "P", 1), (Y, "Y", self.S)):
             _check_field(t, nm, r, B, ld, torch.float64)
         _check_field(target, "target", self.S, B, ld, torch.float32)
+        np_ = n_params(self.widths)
         for t, nm in ((params, "params"), (grads, "grads"), (adam_m, "adam_m"), (adam_v, "adam_v")):
-            if t.dtype != torch.float32 or not t.is_contiguous() or t.numel() != params.numel():
-                raise ValueError(f"{nm}: expected a contiguous float32 tensor like params")
+            _check_params(t, np_, nm)
         if loss is None:
             loss = torch.empty(1, dtype=torch.float32, device=T.device)
+        elif (not isinstance(loss, torch.Tensor) or not loss.is_cuda or loss.dtype != torch.float32
+              or loss.numel() < 1):
+            raise ValueError("loss: expected a CUDA float32 tensor with at least one element")
         _check(lib().chem_dnn_train_step(self._h, B, ld, _ptr(T), _ptr(P), _ptr(Y), _ptr(target),
                                          _ptr(params), _ptr(grads), _ptr(adam_m), _ptr(adam_v),
                                          int(step), float(lr), int(bool(recompute)), _ptr(loss),
@@ -364,6 +438,7 @@ class PropNet:
         self.n_in, self.n_out = self.widths[0], self.widths[-1]
         self.precision = precision
         desc, keep = make_prop_desc(self.widths, precision, in_mean, in_std, out_mean, out_std)
+        _check_params(params, n_params(self.widths))
         nbytes = prop_workspace_bytes(desc)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=params.device)
         base = self.workspace.data_ptr()
@@ -393,6 +468,7 @@ class PropNet:
         return y
 
     def set_params(self, params):
+        _check_params(params, n_params(self.widths))
         _check(lib().chem_prop_set_params(self._h, _ptr(params), _stream()), "chem_prop_set_params")
 
     def close(self):
@@ -420,10 +496,13 @@ def autograd_function():
         @staticmethod
         def forward(ctx, x, params, handle, recompute=False):
             B = x.shape[1]
+            # x's leading dimension: the library indexes every [rows][B]
+            # operand of one call with it
+            ld = int(x.stride(0)) if x.shape[0] > 1 else B
             saved = None
             if not recompute:
-                saved = torch.empty((hidden_total(handle.widths), B), dtype=torch.float32,
-                                    device=x.device)
+                saved = torch.empty((hidden_total(handle.widths), ld), dtype=torch.float32,
+                                    device=x.device)[:, :B]
             out = handle.mlp_forward(x, params, saved)
             ctx.handle = handle
             if recompute:
@@ -437,7 +516,13 @@ def autograd_function():
             tensors = ctx.saved_tensors
             x, params = tensors[0], tensors[1]
             saved = tensors[2] if len(tensors) > 2 else None
-            go = grad_out.contiguous()
+            B = x.shape[1]
+            ld = int(x.stride(0)) if x.shape[0] > 1 else B
+            go = grad_out
+            if go.dim() != 2 or go.stride(1) != 1 or (go.shape[0] > 1 and go.stride(0) != ld):
+                go = torch.empty((grad_out.shape[0], ld), dtype=torch.float32,
+                                 device=grad_out.device)[:, :B]
+                go.copy_(grad_out)
             gp, gx = ctx.handle.mlp_backward(x, params, saved, go, want_grad_x=ctx.needs_input_grad[0])
             return gx, gp, None, None
 

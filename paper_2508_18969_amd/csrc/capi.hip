@@ -68,6 +68,7 @@ namespace {
 
 constexpr size_t kAlign = 256;
 
+
 // Coefficients of the tabulated GELU: per interval i of [-3, 3] (width
 // 0.01), the value, first derivative and half the second derivative of
 // G(x) = x (1 + tanh v) / 2, v = sqrt(2/pi) (x + 0.044715 x^3), at the
@@ -83,6 +84,20 @@ void fill_gelu_table(float *tab) {
     tab[4 * i + 1] = (float)(0.5 * (1.0 + t) + 0.5 * x * s * v1);
     tab[4 * i + 2] = (float)(0.5 * (s * v1 + 0.5 * x * (s * v2 - 2.0 * t * s * v1 * v1)));
     tab[4 * i + 3] = 0.0f;
+  }
+}
+// The FP16 table: the same coefficients rounded once from FP64 to FP16
+// (round to nearest even), 8 bytes per interval.
+void fill_gelu_table16(_Float16 *tab) {
+  const double c = sqrt(2.0 / M_PI), k = 0.044715;
+  for (int i = 0; i < GTAB_N; ++i) {
+    const double x = -3.0 + (i + 0.5) * 0.01;
+    const double v = c * (x + k * x * x * x), t = tanh(v), s = 1.0 - t * t;
+    const double v1 = c * (1.0 + 3.0 * k * x * x), v2 = c * 6.0 * k * x;
+    tab[4 * i + 0] = (_Float16)(0.5 * x * (1.0 + t));
+    tab[4 * i + 1] = (_Float16)(0.5 * (1.0 + t) + 0.5 * x * s * v1);
+    tab[4 * i + 2] = (_Float16)(0.5 * (s * v1 + 0.5 * x * (s * v2 - 2.0 * t * s * v1 * v1)));
+    tab[4 * i + 3] = (_Float16)0.0;
   }
 }
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -117,7 +132,9 @@ int32_t check_desc(const chem_dnn_desc *d) {
   for (int l = 1; l < L; ++l)
     if (d->widths[l] < 1 || d->widths[l] > 4096) return CHEM_DNN_EINVAL;
   if (d->precision < CHEM_DNN_FP32 || d->precision > CHEM_DNN_FP8E4M3) return CHEM_DNN_EINVAL;
-  if (d->gelu_form != CHEM_DNN_GELU_TANH && d->gelu_form != CHEM_DNN_GELU_TABLE) return CHEM_DNN_EINVAL;
+  if (d->gelu_form != CHEM_DNN_GELU_TANH && d->gelu_form != CHEM_DNN_GELU_TABLE &&
+      d->gelu_form != CHEM_DNN_GELU_TABLE16)
+    return CHEM_DNN_EINVAL;
   if (!(d->boxcox_lambda > 0.0) || !isfinite(d->boxcox_lambda)) return CHEM_DNN_EINVAL;
   if (!d->in_mean || !d->in_std) return CHEM_DNN_EINVAL;
   for (int f = 0; f < S + 2; ++f)
@@ -126,6 +143,7 @@ int32_t check_desc(const chem_dnn_desc *d) {
   if ((d->thermo_hf == nullptr) != (d->thermo_cp == nullptr)) return CHEM_DNN_EINVAL;
   if (d->precision == CHEM_DNN_FP8E4M3 && !d->act_amax) return CHEM_DNN_EINVAL;
   if (d->max_batch < 0) return CHEM_DNN_EINVAL;
+  if (d->recompute_chunk < 0 || d->recompute_chunk % 16) return CHEM_DNN_EINVAL;
   if (d->molar_mass)
     for (int s = 0; s < S; ++s)
       if (!(d->molar_mass[s] > 0.0) || !isfinite(d->molar_mass[s])) return CHEM_DNN_EINVAL;
@@ -179,7 +197,7 @@ int32_t plan(const chem_dnn_desc *d, NetLayout *lay, WsPlan *p) {
     off = align_up(off + (size_t)32 * kChunk * sizeof(float));
   }
   p->train = off;
-  off += fused ? train_scratch_bytes(d->widths, d->max_batch) : 0;
+  off += fused ? train_scratch_bytes(d->widths, d->max_batch, d->recompute_chunk) : 0;
   p->total = align_up(off);
   return CHEM_DNN_OK;
 }
@@ -283,7 +301,7 @@ int32_t run_layered(chem_dnn *h, int64_t n, int64_t ld, const double *T, const d
     int cur = 0;
     for (int l = 0; l < h->L && e == hipSuccess; ++l) {
       LayerArgs la{h->wpack[l] ? (const uint8_t *)h->wpack[l] : nullptr, h->bias[l], h->act[cur],
-                   h->act[cur ^ 1], h->obuf, h->lR[l], h->lNQ[l], ncb, 16 * ncb};
+                   h->act[cur ^ 1], h->obuf, h->lR[l], h->lNQ[l], ncb, 16 * ncb, nullptr, 0, 0};
       e = launch_layer(fmt, la, l < h->L - 1, s);
       cur ^= 1;
     }
@@ -407,6 +425,13 @@ int32_t prop_pack(chem_prop *h, const float *params, hipStream_t s) {
   return hip_status(e);
 }
 
+// The fused kernel of the handle's activation form.
+hipError_t (*step_launch(const chem_dnn *h))(const StepArgs &, int, hipStream_t) {
+  return h->gelu_form == CHEM_DNN_GELU_TABLE   ? h->lay.step_tab
+         : h->gelu_form == CHEM_DNN_GELU_TABLE16 ? h->lay.step_tab16
+                                                 : h->lay.step;
+}
+
 int grid_for(const chem_dnn *h, int64_t ntiles) {
   int64_t g = ntiles < h->n_cu ? ntiles : h->n_cu;
   return (int)(g < 1 ? 1 : g);
@@ -416,7 +441,7 @@ int grid_for(const chem_dnn *h, int64_t ntiles) {
 
 extern "C" {
 
-int32_t chem_dnn_abi_version(void) { return 4; }
+int32_t chem_dnn_abi_version(void) { return 5; }
 
 const char *chem_dnn_strerror(int32_t st) {
   switch (st) {
@@ -494,11 +519,16 @@ int32_t chem_dnn_init(const chem_dnn_desc *d, const float *params, void *workspa
     h->wpack[l] = h->ws + p.w[l];
   }
   h->max_batch = d->max_batch;
-  train_scratch_layout(&h->tr, h->ws + p.train, d->widths, d->max_batch);
+  train_scratch_layout(&h->tr, h->ws + p.train, d->widths, d->max_batch, d->recompute_chunk);
   h->thermo = d->thermo_hf ? 1 : 0;
   h->molar = d->molar_mass ? 1 : 0;
   h->gelu_form = d->gelu_form;
-  fill_gelu_table(h->hgtab);
+  if (d->gelu_form == CHEM_DNN_GELU_TABLE16) {
+    memset(h->hgtab, 0, sizeof(h->hgtab));
+    fill_gelu_table16((_Float16 *)h->hgtab);       // (the first 4.8 KB of the buffer)
+  } else {
+    fill_gelu_table(h->hgtab);
+  }
 
   // constants
   const double lam = d->boxcox_lambda;
@@ -572,8 +602,7 @@ int32_t chem_dnn_step(chem_dnn *h, int64_t n, int64_t ld, const double *T, const
   if (h->layered)
     return run_layered(h, n, ld, T, P, Y, Y_out, T_out, nullptr, 0.0, n_bad, (hipStream_t)stream);
   StepArgs a = step_args(h, n, ld, T, P, Y, Y_out, T_out, n_bad);
-  auto launch = h->gelu_form == CHEM_DNN_GELU_TABLE ? h->lay.step_tab : h->lay.step;
-  return hip_status(launch(a, grid_for(h, a.ntiles), (hipStream_t)stream));
+  return hip_status(step_launch(h)(a, grid_for(h, a.ntiles), (hipStream_t)stream));
 }
 
 int32_t chem_dnn_step_source(chem_dnn *h, int64_t n, int64_t ld, const double *T,
@@ -592,8 +621,7 @@ int32_t chem_dnn_step_source(chem_dnn *h, int64_t n, int64_t ld, const double *T
   StepArgs a = step_args(h, n, ld, T, P, Y, Y_out, T_out, n_bad);
   a.omega = omega;
   a.inv_dt = 1.0 / dt;
-  auto launch = h->gelu_form == CHEM_DNN_GELU_TABLE ? h->lay.step_tab : h->lay.step;
-  return hip_status(launch(a, grid_for(h, a.ntiles), (hipStream_t)stream));
+  return hip_status(step_launch(h)(a, grid_for(h, a.ntiles), (hipStream_t)stream));
 }
 
 int32_t chem_dnn_calibrate(chem_dnn *h, int64_t n, int64_t ld, const double *T, const double *P,
@@ -606,7 +634,9 @@ int32_t chem_dnn_calibrate(chem_dnn *h, int64_t n, int64_t ld, const double *T, 
   if (!T || !P || !Y) return CHEM_DNN_EINVAL;
   StepArgs a = step_args(h, n, ld, T, P, Y, nullptr, nullptr, nullptr);
   a.amax = amax;
-  auto launch = h->gelu_form == CHEM_DNN_GELU_TABLE ? h->lay.calib_tab : h->lay.calib;
+  auto launch = h->gelu_form == CHEM_DNN_GELU_TABLE   ? h->lay.calib_tab
+                : h->gelu_form == CHEM_DNN_GELU_TABLE16 ? h->lay.calib_tab16
+                                                        : h->lay.calib;
   return hip_status(launch(a, grid_for(h, a.ntiles), s));
 }
 
@@ -665,6 +695,61 @@ int32_t chem_dnn_destroy(chem_dnn *h) {
   if (!h) return CHEM_DNN_EINVAL;
   delete h;
   return CHEM_DNN_OK;
+}
+
+int32_t chem_dnn_debug_layers(chem_dnn *h, int64_t n, int64_t ld, const double *T,
+                              const double *P, const double *Y, float *qin, float *acc,
+                              void *stream) {
+  if (!h || n < 0 || ld < n || n > CHEM_DNN_DEBUG_MAX_CELLS) return CHEM_DNN_EINVAL;
+  if (n == 0) return CHEM_DNN_OK;
+  if (!T || !P || !Y || !qin || !acc) return CHEM_DNN_EINVAL;
+  if (h->gelu_form != CHEM_DNN_GELU_TANH) return CHEM_DNN_EUNSUPPORTED;
+  hipStream_t s = (hipStream_t)stream;
+  int in_row[8], acc_row[8];
+  for (int l = 0, ri = 0, ra = 0; l < h->L; ++l) {
+    in_row[l] = ri;
+    acc_row[l] = ra;
+    ri += h->widths[l];
+    ra += h->widths[l + 1];
+  }
+  if (!h->layered) {
+    if (!h->lay.dbg) return CHEM_DNN_EUNSUPPORTED;
+    StepArgs a = step_args(h, n, ld, T, P, Y, nullptr, nullptr, nullptr);
+    a.dbg_in = qin;
+    a.dbg_acc = acc;
+    for (int l = 0; l < 4; ++l) {
+      a.dbg_in_row[l] = in_row[l];
+      a.dbg_acc_row[l] = acc_row[l];
+    }
+    return hip_status(h->lay.dbg(a, grid_for(h, a.ntiles), s));
+  }
+  // layer by layer: one chunk (n <= CHEM_DNN_DEBUG_MAX_CELLS < kChunk)
+  const int fmt = h->prec;
+  const int nc = (int)n, ncb = (nc + 255) / 256 * 16;
+  PrepArgs pa{T, P, Y, ld, 0, nc, ncb, h->act[0], h->fc, h->dc, h->S};
+  hipError_t e = launch_prep(fmt, pa, s);
+  if (e == hipSuccess) e = launch_frag_decode(fmt, h->act[0], ncb, h->widths[0], nc, qin, s);
+  int cur = 0;
+  for (int l = 0; l < h->L && e == hipSuccess; ++l) {
+    const bool hidden = l < h->L - 1;
+    LayerArgs la{(const uint8_t *)h->wpack[l], h->bias[l], h->act[cur], h->act[cur ^ 1], h->obuf,
+                 h->lR[l], h->lNQ[l], ncb, 16 * ncb, nullptr, 0, 0};
+    if (hidden) {
+      la.dbg_acc = acc + (size_t)acc_row[l] * nc;
+      la.dbg_rows = h->widths[l + 1];
+      la.dbg_n = nc;
+      e = launch_layer_dbg(fmt, la, s);
+      if (e == hipSuccess)
+        e = launch_frag_decode(fmt, h->act[cur ^ 1], ncb, h->widths[l + 1], nc,
+                               qin + (size_t)in_row[l + 1] * nc, s);
+    } else {
+      e = launch_layer(fmt, la, false, s);
+      if (e == hipSuccess)
+        e = launch_copy_rows(h->obuf, 16 * ncb, h->S, nc, acc + (size_t)acc_row[l] * nc, s);
+    }
+    cur ^= 1;
+  }
+  return hip_status(e);
 }
 
 int32_t chem_prop_workspace_bytes(const chem_prop_desc *desc, size_t *bytes) {
@@ -789,7 +874,7 @@ int32_t chem_prop_eval(chem_prop *h, int64_t n, int64_t ld, const double *x, dou
     int cur = 0;
     for (int l = 0; l < h->L && e == hipSuccess; ++l) {
       LayerArgs la{(const uint8_t *)h->wpack[l], h->bias[l], h->act[cur], h->act[cur ^ 1],
-                   h->obuf, h->lR[l], h->lNQ[l], ncb, 16 * ncb};
+                   h->obuf, h->lR[l], h->lNQ[l], ncb, 16 * ncb, nullptr, 0, 0};
       e = launch_layer(h->prec, la, l < h->L - 1, s);
       cur ^= 1;
     }

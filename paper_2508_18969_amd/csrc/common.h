@@ -64,6 +64,19 @@ __device__ __forceinline__ float gelu_tab(float x, const f4 *tab) {
   return x < -3.0f ? 0.0f : (x > 3.0f ? x : y);
 }
 
+// The same table with FP16 coefficients (c0, c1, c2, 0) per interval (the
+// paper implements FP32 and FP16 tabulation, Sec. 3.3.2): 8 bytes per
+// interval, converted to FP32 on use; the polynomial is evaluated in FP32.
+typedef _Float16 h4v __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float gelu_tab16(float x, const h4v *tab) {
+  int i = (int)((x + 3.0f) * 100.0f);
+  i = i < 0 ? 0 : (i > 599 ? 599 : i);
+  const float d = x - __builtin_fmaf((float)i, 0.01f, -2.995f);
+  const h4v c = tab[i];
+  const float y = __builtin_fmaf(__builtin_fmaf((float)c[2], d, (float)c[1]), d, (float)c[0]);
+  return x < -3.0f ? 0.0f : (x > 3.0f ? x : y);
+}
+
 // Y^lam in FP32 from an FP64 mass fraction, via the exponent split
 // y = m 2^e (m in [1, 2)) so that values far below FLT_MIN keep their
 // magnitude.  Non-positive, NaN or subnormal-double inputs give 0
@@ -81,13 +94,16 @@ __device__ __forceinline__ float ypow(double y, float lam) {
 // The change Y* - Y of one mass fraction y whose Box-Cox value moves by
 // wv = lam delta (delta = the network output after the output statistics):
 // Y* = (max(0, y^lam + wv))^(1/lam).  For a small step it is taken relative to
-// y, Y* - y = y ((1 + t)^(1/lam) - 1) with t = wv / y^lam, which has no
-// cancellation.  Both forms are evaluated without branches on the hardware
-// log2 / exp2.
+// y, Y* - y = y ((1 + t)^(1/lam) - 1) with t = wv / y^lam, so the change keeps
+// its relative accuracy.  The caller adds y back: y + y e with e = (1 + t)^(1/lam)
+// - 1 cancels by 1/(1 + e), so the relative form is used only for t >= -0.1
+// (1 + e >= 0.9^10 = 0.35, at most a 1.9x loss; for t > 0 nothing cancels);
+// a larger decrease takes Y* itself.  Both forms are evaluated without
+// branches on the hardware log2 / exp2.
 __device__ __forceinline__ double inv_change(double y, float wv, float lam, float inv_lam) {
   const float b = ypow(y, lam);
   const float t = wv * __builtin_amdgcn_rcpf(b);
-  const bool small = b > 0.0f && __builtin_fabsf(t) <= 0.5f;
+  const bool small = b > 0.0f && t >= -0.1f && t <= 0.5f;
   const float u = 1.0f + t;
   // log2(1 + t) = log2(u) t / (u - 1) for the rounded u (exact when u == 1)
   // (both arms of each choice are computed and pinned, so that the choice is
@@ -147,6 +163,8 @@ struct OpF32 {
   }
   // store 4 values (already scaled) into 4 consecutive slots
   static __device__ __forceinline__ void store4(uint8_t *p, f4 v) { *(f4 *)p = v; }
+  // the operand value a stored v becomes, as FP32
+  static __device__ __forceinline__ float q(float v) { return v; }
 };
 
 struct OpBF16 {
@@ -163,6 +181,7 @@ struct OpBF16 {
     o[0] = (__bf16)v[0]; o[1] = (__bf16)v[1]; o[2] = (__bf16)v[2]; o[3] = (__bf16)v[3];
     *(b4 *)p = o;
   }
+  static __device__ __forceinline__ float q(float v) { return (float)(__bf16)v; }
 };
 
 struct OpF16 {
@@ -179,6 +198,7 @@ struct OpF16 {
     o[0] = (_Float16)v[0]; o[1] = (_Float16)v[1]; o[2] = (_Float16)v[2]; o[3] = (_Float16)v[3];
     *(q4 *)p = o;
   }
+  static __device__ __forceinline__ float q(float v) { return (float)(_Float16)v; }
 };
 
 // OCP FP8 E4M3 with the K=128 f8f6f4 matrix instruction (unit block scales:
@@ -200,6 +220,12 @@ struct OpF8 {
     return __builtin_amdgcn_cvt_pk_fp8_f32(c, d, w, true);
   }
   static __device__ __forceinline__ void store4(uint8_t *p, f4 v) { *(uint32_t *)p = pack4(v); }
+  // the same clamp and conversion as pack4, decoded back to FP32
+  static __device__ __forceinline__ float q(float v) {
+    const uint32_t w = __builtin_amdgcn_cvt_pk_fp8_f32(__builtin_amdgcn_fmed3f(v, -448.0f, 448.0f),
+                                                       0.0f, 0, false);
+    return __builtin_amdgcn_cvt_f32_fp8((int)w, 0);
+  }
 };
 
 template <int A, int B> struct Max { static constexpr int v = A > B ? A : B; };

@@ -46,7 +46,8 @@ struct StepArgs {
   const float *fc;       // FConst block
   const double *dc;      // DConst block
   float *amax;           // calibration output [4] (bit pattern max)
-  const float *gtab;     // tabulated GELU: [GTAB_N][4] (c0, c1, c2, 0) per interval
+  const void *gtab;      // tabulated GELU: [GTAB_N][4] (c0, c1, c2, 0) per interval,
+                         // FP32 or FP16
   double *omega;         // species source terms [S][ld], or NULL
   double inv_dt;         // 1 / dt of the source terms
   int S, thermo;
@@ -54,6 +55,12 @@ struct StepArgs {
   const double *x;       // input fields [D][ld]
   double *y;             // outputs [K][ld] (output k on row k + 2 of layer 4)
   int D, K;
+  // layer dump (the kernel's debug mode): per layer l, its input operand
+  // values (decoded to FP32) in rows dbg_in_row[l] .. + widths[l] of dbg_in
+  // and its FP32 accumulators in rows dbg_acc_row[l] .. + widths[l+1] of
+  // dbg_acc, both [rows][n]
+  float *dbg_in, *dbg_acc;
+  int dbg_in_row[4], dbg_acc_row[4];
 };
 
 // Tabulated GELU: GTAB_N intervals of width 1/GTAB_INV_H from GTAB_LO.
@@ -68,6 +75,10 @@ struct LayerArgs {
   uint8_t *Y;            // hidden layers: output B fragments [16 R / KS][NCB]
   float *O;              // output layer: FP32 [16 R][ldo]
   int R, NQ, NCB, ldo;   // row-blocks, input k-steps, cell-blocks of the chunk, O's stride
+  // debug mode of hidden layers: FP32 accumulators of rows < dbg_rows and
+  // cells < dbg_n into dbg_acc[row * dbg_n + cell]
+  float *dbg_acc;
+  int dbg_rows, dbg_n;
 };
 struct PrepArgs {
   const double *T, *P, *Y;
@@ -121,6 +132,13 @@ hipError_t launch_layer(int fmt, const LayerArgs &a, bool hidden, hipStream_t s)
 hipError_t launch_post(const PostArgs &a, hipStream_t s);
 hipError_t launch_prop_prep(int fmt, const PropPrepArgs &a, hipStream_t s);
 hipError_t launch_prop_post(const PropPostArgs &a, hipStream_t s);
+// debug: hidden layer with its accumulators dumped; the operand values of B
+// fragments X ([NQ][NCB], features < K, cells < n) decoded into out[f * n + c]
+hipError_t launch_layer_dbg(int fmt, const LayerArgs &a, hipStream_t s);
+hipError_t launch_frag_decode(int fmt, const uint8_t *X, int NCB, int K, int n, float *out,
+                              hipStream_t s);
+hipError_t launch_copy_rows(const float *src, int ld_src, int rows, int n, float *dst,
+                            hipStream_t s);
 
 // Shape and layout of one compiled network configuration.
 struct NetLayout {
@@ -131,8 +149,11 @@ struct NetLayout {
   // launches
   hipError_t (*step)(const StepArgs &, int grid, hipStream_t);
   hipError_t (*step_tab)(const StepArgs &, int grid, hipStream_t);   // tabulated GELU
+  hipError_t (*step_tab16)(const StepArgs &, int grid, hipStream_t); // ... FP16 table
   hipError_t (*calib)(const StepArgs &, int grid, hipStream_t);  // FP32 only, else null
   hipError_t (*calib_tab)(const StepArgs &, int grid, hipStream_t);
+  hipError_t (*calib_tab16)(const StepArgs &, int grid, hipStream_t);
+  hipError_t (*dbg)(const StepArgs &, int grid, hipStream_t);    // layer dump
   hipError_t (*prepare)();     // one-time function attributes
 };
 // The same for the kernel's property mode (hidden widths h1, h2, h3); only
@@ -142,6 +163,14 @@ bool find_prop_layout(int p, int h1, int h2, int h3, NetLayout *out);
 // Finds the compiled configuration for hidden widths (h1, h2, h3) in
 // precision p; returns false when the library has none.
 bool find_layout(int p, int h1, int h2, int h3, NetLayout *out);
+// (per operand format, in step_<format>.hip)
+bool find_layout_fp32(int h1, int h2, int h3, NetLayout *out);
+bool find_layout_bf16(int h1, int h2, int h3, NetLayout *out);
+bool find_layout_fp16(int h1, int h2, int h3, NetLayout *out);
+bool find_layout_fp8(int h1, int h2, int h3, NetLayout *out);
+bool find_prop_layout_fp32(int h1, int h2, int h3, NetLayout *out);
+bool find_prop_layout_bf16(int h1, int h2, int h3, NetLayout *out);
+bool find_prop_layout_fp16(int h1, int h2, int h3, NetLayout *out);
 
 // Weight packing (kernels in step.hip).
 hipError_t launch_weight_amax(const float *W, int64_t count, uint32_t *amax_bits, hipStream_t s);

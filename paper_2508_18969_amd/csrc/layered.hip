@@ -75,7 +75,8 @@ __device__ __forceinline__ void dma_frag(const uint8_t *src, uint8_t *dst, int l
 // so that the reads of k-step q + 1 overlap the products of k-step q.  Four
 // stages: the copies of k-step q + 3 are issued once every wave has read the
 // fragments of k-step q (and so is done with the stage of q - 1).
-template <class Op, int WRB, int WR, int WCB, int WC, bool ACT>
+// DBG (hidden layers): the accumulators are also written to a.dbg_acc.
+template <class Op, int WRB, int WR, int WCB, int WC, bool ACT, bool DBG = false>
 __global__ __launch_bounds__(WR * WC * 64, 1) void layer_kernel(LayerArgs a) {
   constexpr int NW = WR * WC;                         // waves
   static_assert(Op::FRAG == 16, "16-byte fragments");
@@ -169,6 +170,18 @@ __global__ __launch_bounds__(WR * WC * 64, 1) void layer_kernel(LayerArgs a) {
     }
   }
 
+  if constexpr (DBG) {
+#pragma unroll
+    for (int i = 0; i < WRB; ++i)
+#pragma unroll
+      for (int j = 0; j < WCB; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * (rb0 + wr * WRB + i) + 4 * g + r;
+          const int cell = 16 * (cb0 + wc * WCB + j) + cl;
+          if (row < a.dbg_rows && cell < a.dbg_n) a.dbg_acc[(size_t)row * a.dbg_n + cell] = acc[i][j][r];
+        }
+  }
   if constexpr (ACT) {
     // GELU, then the next layer's B fragments: output row 16 rb + 4 g + r is
     // input feature of k-step rb / RPQ, slot 4 (rb % RPQ) + r
@@ -297,8 +310,11 @@ __global__ __launch_bounds__(256) void post_kernel(PostArgs a) {
     y[s] = a.Y[(int64_t)s * a.ld + i];
     bad |= !__builtin_isfinite(y[s]);
     const float o = a.O[(size_t)s * a.ldo + c];
-    const double v = y[s] + inv_change(y[s], __builtin_fmaf(o, a.fc[FConst::PA + rho], a.fc[FConst::PB + rho]),
-                                       lam, inv_lam);
+    const float wv = __builtin_fmaf(o, a.fc[FConst::PA + rho], a.fc[FConst::PB + rho]);
+    const double v = y[s] + inv_change(y[s], wv, lam, inv_lam);
+    // a NaN network output or a non-finite result flags the cell (the inverse
+    // transform takes a NaN base like a negative one; the clamp turns NaN into 0)
+    bad |= __builtin_isnan(wv) || !__builtin_isfinite(v);
     yh[s] = v > 0.0 ? v : 0.0;
     ssum += yh[s];
     h0 += y[s] * (a.dc[DConst::HF + rho] + a.dc[DConst::CP + rho] * (T - t_ref));
@@ -338,6 +354,33 @@ __global__ __launch_bounds__(256) void prop_post_kernel(PropPostArgs a) {
   a.y[(int64_t)k * a.ld + a.n0 + c] = __builtin_fma(o, a.pc[PConst::OUT_SD + k], a.pc[PConst::OUT_MU + k]);
 }
 
+// ------------------------------------------------------------------ debug
+// Operand value of feature f < K of cell c < n in the B fragments X
+// ([NQ][NCB] fragments of 64 lanes x 16 bytes), decoded to FP32: the
+// inverse of frag_feature within a k-step, f = KS q + 16 (j / 4) + 4 g + j % 4.
+template <class Op>
+__global__ __launch_bounds__(256) void frag_decode_kernel(const uint8_t *X, int NCB, int K, int n,
+                                                          float *out) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (int64_t)K * n) return;
+  const int f = (int)(t / n), c = (int)(t % n);
+  const int q = f / Op::KS, rr = f % Op::KS;
+  const int j = 4 * (rr / 16) + rr % 4, g = (rr % 16) / 4;
+  const uint8_t *p = X + ((size_t)(q * NCB + c / 16) * 64 + g * 16 + c % 16) * 16 + j * Op::EB;
+  float v;
+  if constexpr (__is_same(Op, OpF32)) v = *(const float *)p;
+  else if constexpr (__is_same(Op, OpBF16)) v = (float)*(const __bf16 *)p;
+  else v = (float)*(const _Float16 *)p;
+  out[t] = v;
+}
+
+__global__ __launch_bounds__(256) void copy_rows_kernel(const float *src, int ld_src, int rows, int n,
+                                                        float *dst) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (int64_t)rows * n) return;
+  dst[t] = src[(t / n) * (int64_t)ld_src + t % n];
+}
+
 // ------------------------------------------------------------------ launchers
 namespace {
 
@@ -371,11 +414,53 @@ hipError_t launch_layer_op(const LayerArgs &a, bool hidden, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <class Op>
+hipError_t launch_layer_dbg_op(const LayerArgs &a, hipStream_t s) {
+  auto k = layer_kernel<Op, HWRB, HWR, HWCB, HWC, true, true>;
+  const int grid = (a.R / 16) * (a.NCB / 16);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(64 * HWR * HWC), LDS_HIDDEN, s, a);
+  return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_layer_dbg(int fmt, const LayerArgs &a, hipStream_t s) {
+  switch (fmt) {
+    case 0: return launch_layer_dbg_op<OpF32>(a, s);
+    case 1: return launch_layer_dbg_op<OpBF16>(a, s);
+    case 2: return launch_layer_dbg_op<OpF16>(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_frag_decode(int fmt, const uint8_t *X, int NCB, int K, int n, float *out,
+                              hipStream_t s) {
+  const int64_t total = (int64_t)K * n;
+  if (total <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((total + 255) / 256));
+  switch (fmt) {
+    case 0: hipLaunchKernelGGL(frag_decode_kernel<OpF32>, grid, dim3(256), 0, s, X, NCB, K, n, out); break;
+    case 1: hipLaunchKernelGGL(frag_decode_kernel<OpBF16>, grid, dim3(256), 0, s, X, NCB, K, n, out); break;
+    case 2: hipLaunchKernelGGL(frag_decode_kernel<OpF16>, grid, dim3(256), 0, s, X, NCB, K, n, out); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_rows(const float *src, int ld_src, int rows, int n, float *dst, hipStream_t s) {
+  const int64_t total = (int64_t)rows * n;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(copy_rows_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, src,
+                     ld_src, rows, n, dst);
+  return hipGetLastError();
+}
 
 // The layer kernels use more than the default 64 KiB of LDS.
 hipError_t layered_prepare() {
   hipError_t e = set_lds(layer_kernel<OpF32, HWRB, HWR, HWCB, HWC, true>, LDS_HIDDEN);
+  if (e == hipSuccess) e = set_lds(layer_kernel<OpF32, HWRB, HWR, HWCB, HWC, true, true>, LDS_HIDDEN);
+  if (e == hipSuccess) e = set_lds(layer_kernel<OpBF16, HWRB, HWR, HWCB, HWC, true, true>, LDS_HIDDEN);
+  if (e == hipSuccess) e = set_lds(layer_kernel<OpF16, HWRB, HWR, HWCB, HWC, true, true>, LDS_HIDDEN);
   if (e == hipSuccess) e = set_lds(layer_kernel<OpBF16, HWRB, HWR, HWCB, HWC, true>, LDS_HIDDEN);
   if (e == hipSuccess) e = set_lds(layer_kernel<OpF16, HWRB, HWR, HWCB, HWC, true>, LDS_HIDDEN);
   if (e == hipSuccess) e = set_lds(layer_kernel<OpF32, 2, 1, 2, 8, false>, LDS_OUT);

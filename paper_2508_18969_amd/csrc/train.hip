@@ -381,10 +381,11 @@ __global__ __launch_bounds__(256) void fc_kernel(GemmArgs g, int nx, int ny) {
 // Sums of split partials for two outputs in one launch: output o < n0 is
 // o0[o] = sum_z p0[z * s0 + o], the next n1 are o1 from p1 likewise.  A
 // workgroup takes 64 outputs; its four waves sum a quarter of the splits each,
-// in increasing z, and the four quarter sums are added in wave order.
+// in increasing z, and the four quarter sums are added in wave order.  With
+// `acc` the sum is added to the output (the gradient of a later chunk).
 __global__ __launch_bounds__(256) void reduce_parts2_kernel(const float *p0, int64_t s0, int64_t n0,
                                                             float *o0, const float *p1, int64_t s1,
-                                                            int64_t n1, float *o1, int nz) {
+                                                            int64_t n1, float *o1, int nz, int accum) {
   __shared__ float q[4][64];
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t o = blockIdx.x * (int64_t)64 + l;
@@ -399,13 +400,13 @@ __global__ __launch_bounds__(256) void reduce_parts2_kernel(const float *p0, int
   __syncthreads();
   if (w == 0 && valid) {
     const float t = ((q[0][l] + q[1][l]) + q[2][l]) + q[3][l];
-    if (first) o0[o] = t;
-    else o1[o - n0] = t;
+    float *dst = first ? o0 + o : o1 + (o - n0);
+    *dst = accum ? *dst + t : t;
   }
 }
 
-// out[m] = sum_b dz[m * ld + b]: one workgroup per row, fixed-order tree.
-__global__ void rowsum_kernel(const float *dz, int64_t ld, int64_t B, float *out) {
+// out[m] = sum_b dz[m * ld + b] (+= with acc): one workgroup per row, fixed-order tree.
+__global__ void rowsum_kernel(const float *dz, int64_t ld, int64_t B, float *out, int acc) {
   __shared__ float red[256];
   const int64_t m = blockIdx.x;
   float s = 0.0f;
@@ -416,15 +417,16 @@ __global__ void rowsum_kernel(const float *dz, int64_t ld, int64_t B, float *out
     if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[m] = red[0];
+  if (threadIdx.x == 0) out[m] = acc ? out[m] + red[0] : red[0];
 }
 
-// dO = 2 (o - t) / (B S); per-block partial sums of (o - t)^2.
+// dO = 2 (o - t) / denom over B samples (denom = batch x species of the whole
+// step); per-block partial sums of (o - t)^2.
 __global__ void mse_kernel(const float *o, int64_t ldo, const float *t, int64_t ldt, int S,
-                           int64_t B, float *dO, float *lpart) {
+                           int64_t B, double denom, float *dO, float *lpart) {
   __shared__ float red[256];
   const int64_t n = (int64_t)S * B;
-  const float inv = 2.0f / (float)((double)B * S);
+  const float inv = 2.0f / (float)denom;
   float s = 0.0f;
   for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
     const int64_t sp = e / B, b = e % B;
@@ -442,14 +444,22 @@ __global__ void mse_kernel(const float *o, int64_t ldo, const float *t, int64_t 
 }
 
 // One wave: lane l sums partials l, l + 64, ... in order, then a fixed
-// butterfly over the lanes (lane 0's order is the same on every run).
-__global__ void loss_final_kernel(const float *lpart, int nb, double denom, float *loss) {
+// butterfly over the lanes (lane 0's order is the same on every run): the
+// loss sum of one chunk.
+__global__ void loss_chunk_kernel(const float *lpart, int nb, double *chunk_sum) {
   const int l = threadIdx.x;
   double s = 0.0;
   for (int i = l; i < nb; i += 64) s += (double)lpart[i];
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
-  if (l == 0) *loss = (float)(s / denom);
+  if (l == 0) *chunk_sum = s;
+}
+// The step's loss: the chunk sums in chunk order, over batch x species.
+__global__ void loss_final_kernel(const double *chunk_sum, int nchunks, double denom, float *loss) {
+  if (threadIdx.x != 0) return;
+  double s = 0.0;
+  for (int k = 0; k < nchunks; ++k) s += chunk_sum[k];
+  *loss = (float)(s / denom);
 }
 
 // Normalised network input from the FP64 state, the same arithmetic as the
@@ -558,10 +568,11 @@ hipError_t forward(const int *w, int64_t B, const float *x, int64_t ldx, const f
   return hipSuccess;
 }
 
-// Backward given dL/d out (gout [S][ldg]) and the pre-activations z.
+// Backward given dL/d out (gout [S][ldg]) and the pre-activations z; the
+// weight and bias gradients are written, or with `acc` added to gparams.
 hipError_t backward(const int *w, int64_t B, const float *x, int64_t ldx, const float *params,
                     const float *z, int64_t ldz, const float *gout, int64_t ldg, float *gparams,
-                    float *gx, int64_t ldgx, TrainScratch *t, hipStream_t s) {
+                    float *gx, int64_t ldgx, TrainScratch *t, hipStream_t s, int acc) {
   int64_t zoffs[4] = {0, w[1], (int64_t)w[1] + w[2], 0};
   const float *dZ = gout;
   int64_t lddz = ldg;
@@ -598,9 +609,9 @@ hipError_t backward(const int *w, int64_t B, const float *x, int64_t ldx, const 
     const int64_t nw = (int64_t)N * K, nb = direct ? N : 0;
     hipLaunchKernelGGL(reduce_parts2_kernel, dim3(blocks_for(nw + nb, 64)), dim3(256), 0, s,
                        (const float *)t->part, nw, nw, gW, (const float *)t->bpart, (int64_t)N, nb,
-                       gW + (size_t)N * K, nsplit);
+                       gW + (size_t)N * K, nsplit, acc);
     if (!direct)
-      hipLaunchKernelGGL(rowsum_kernel, dim3(N), dim3(256), 0, s, dZ, lddz, B, gW + (size_t)N * K);
+      hipLaunchKernelGGL(rowsum_kernel, dim3(N), dim3(256), 0, s, dZ, lddz, B, gW + (size_t)N * K, acc);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // dZ_(l-1) = (W_l^T dZ_l) * GELU'(z_(l-1)), or grad_x for l = 0
     if (l > 0 || gx) {
@@ -608,7 +619,7 @@ hipError_t backward(const int *w, int64_t B, const float *x, int64_t ldx, const 
       d.A = params + param_off(w, l); d.sam = 1; d.sak = K;    // W^T: (k, n) -> W[n][k]
       d.B = dZ; d.sbk = lddz; d.sbn = 1;
       float *dst = (l > 0) ? t->dz[pp] : gx;
-      const int64_t ldd = (l > 0) ? t->cap : ldgx;
+      const int64_t ldd = (l > 0) ? t->ld : ldgx;
       d.C = dst; d.scm = ldd; d.scn = 1;
       d.M = K; d.N = (int)B; d.K = N; d.kchunk = N;
       d.zprev = (l > 0) ? z + zoffs[l - 1] * ldz : nullptr;
@@ -625,105 +636,139 @@ hipError_t backward(const int *w, int64_t B, const float *x, int64_t ldx, const 
 
 }  // namespace
 
-size_t train_scratch_bytes(const int *w, int64_t cap) {
+namespace {
+
+// Samples the per-sample buffers hold: the whole batch, or one chunk.
+int64_t chunk_of(int64_t cap, int64_t chunk) { return chunk > 0 && chunk < cap ? chunk : cap; }
+int64_t n_chunks(int64_t B, int64_t ld) { return (B + ld - 1) / ld; }
+
+}  // namespace
+
+size_t train_scratch_bytes(const int *w, int64_t cap, int64_t chunk) {
   if (cap <= 0) return 0;
+  const int64_t ld = chunk_of(cap, chunk);
   const int64_t H = (int64_t)w[1] + w[2] + w[3];
   int64_t mx = w[4];
   for (int l = 1; l < 4; ++l) mx = mx > w[l] ? mx : w[l];
-  size_t f = (size_t)cap * (w[0] + H + w[4] + 2 * mx) + (size_t)kMaxSplit * max_layer_weights(w) +
+  size_t f = (size_t)ld * (w[0] + H + w[4] + 2 * mx) + (size_t)kMaxSplit * max_layer_weights(w) +
              (size_t)kMaxSplitAll * mx + 1024;
-  return f * sizeof(float) + 9 * 256;
+  return f * sizeof(float) + (size_t)n_chunks(cap, ld) * sizeof(double) + 10 * 256;
 }
 
-void train_scratch_layout(TrainScratch *t, uint8_t *base, const int *w, int64_t cap) {
+void train_scratch_layout(TrainScratch *t, uint8_t *base, const int *w, int64_t cap, int64_t chunk) {
   *t = TrainScratch{};
   t->cap = cap;
   if (cap <= 0) return;
+  const int64_t ld = chunk_of(cap, chunk);
+  t->ld = ld;
   const int64_t H = (int64_t)w[1] + w[2] + w[3];
   int64_t mx = w[4];
   for (int l = 1; l < 4; ++l) mx = mx > w[l] ? mx : w[l];
-  auto take = [&](size_t floats) {
-    float *p = (float *)base;
-    base += (floats * sizeof(float) + 255) / 256 * 256;
+  auto take = [&](size_t bytes) {
+    uint8_t *p = base;
+    base += (bytes + 255) / 256 * 256;
     return p;
   };
-  t->x = take((size_t)cap * w[0]);
-  t->z = take((size_t)cap * H);
-  t->out = take((size_t)cap * w[4]);
-  t->dz[0] = take((size_t)cap * mx);
-  t->dz[1] = take((size_t)cap * mx);
-  t->part = take((size_t)kMaxSplit * max_layer_weights(w));
-  t->bpart = take((size_t)kMaxSplitAll * mx);
-  t->lpart = take(1024);
+  t->x = (float *)take((size_t)ld * w[0] * sizeof(float));
+  t->z = (float *)take((size_t)ld * H * sizeof(float));
+  t->out = (float *)take((size_t)ld * w[4] * sizeof(float));
+  t->dz[0] = (float *)take((size_t)ld * mx * sizeof(float));
+  t->dz[1] = (float *)take((size_t)ld * mx * sizeof(float));
+  t->part = (float *)take((size_t)kMaxSplit * max_layer_weights(w) * sizeof(float));
+  t->bpart = (float *)take((size_t)kMaxSplitAll * mx * sizeof(float));
+  t->lpart = (float *)take(1024 * sizeof(float));
+  t->closs = (double *)take((size_t)n_chunks(cap, ld) * sizeof(double));
 }
 
 hipError_t train_prepare() { return hipSuccess; }
 
+// Forward over B samples of x [D][ld]: with `saved` the pre-activations of the
+// whole batch go there ([H][ld]); without, chunk by chunk through the scratch.
 hipError_t train_mlp_forward(const int *w, int64_t B, int64_t ld, const float *x,
                              const float *params, float *out, float *saved, TrainScratch *t,
                              hipStream_t s) {
   if (saved) return forward(w, B, x, ld, params, saved, ld, out, ld, s);
   if (B > t->cap) return hipErrorInvalidValue;
-  return forward(w, B, x, ld, params, t->z, t->cap, out, ld, s);
+  for (int64_t c0 = 0; c0 < B; c0 += t->ld) {
+    const int64_t bc = B - c0 < t->ld ? B - c0 : t->ld;
+    hipError_t e = forward(w, bc, x + c0, ld, params, t->z, t->ld, out + c0, ld, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
+// Backward over B samples, chunk by chunk (one chunk when the scratch holds
+// the whole batch): the chunk's pre-activations are copied from `saved`
+// ([H][ld]) or, without it, recomputed from x; the weight and bias gradients
+// of later chunks are added in chunk order.  The schedule and the arithmetic
+// per chunk are the same whether the pre-activations were saved or
+// recomputed, so both give the same gradient bit for bit.
 hipError_t train_mlp_backward(const int *w, int64_t B, int64_t ld, const float *x,
                               const float *params, const float *saved, const float *grad_out,
                               float *grad_params, float *grad_x, TrainScratch *t, hipStream_t s) {
   if (B > t->cap) return hipErrorInvalidValue;
-  const float *z = saved;
-  int64_t ldz = ld;
-  if (!z) {
-    hipError_t e = forward(w, B, x, ld, params, t->z, t->cap, t->out, t->cap, s);
-    if (e != hipSuccess) return e;
-    z = t->z;
-    ldz = t->cap;
-  }
-  if (ldz != t->cap) {
-    // the fused GELU' epilogue reads z with the scratch leading dimension
-    for (int l = 0; l < 3; ++l) {
-      int64_t off = 0;
-      for (int i = 0; i < l; ++i) off += w[i + 1];
-      hipError_t e = hipMemcpy2DAsync(t->z + off * t->cap, t->cap * sizeof(float),
-                                      z + off * ldz, ldz * sizeof(float), B * sizeof(float),
-                                      w[l + 1], hipMemcpyDeviceToDevice, s);
-      if (e != hipSuccess) return e;
+  const int64_t H = (int64_t)w[1] + w[2] + w[3];
+  int k = 0;
+  for (int64_t c0 = 0; c0 < B; c0 += t->ld, ++k) {
+    const int64_t bc = B - c0 < t->ld ? B - c0 : t->ld;
+    const float *z = t->z;
+    hipError_t e = hipSuccess;
+    if (saved && c0 == 0 && bc == B && ld == t->ld) {
+      z = saved;                 // (already in the scratch's layout)
+    } else if (saved) {
+      // the fused GELU' epilogue reads z with the scratch leading dimension
+      e = hipMemcpy2DAsync(t->z, t->ld * sizeof(float), saved + c0, ld * sizeof(float),
+                           bc * sizeof(float), H, hipMemcpyDeviceToDevice, s);
+    } else {
+      e = forward(w, bc, x + c0, ld, params, t->z, t->ld, t->out, t->ld, s);
     }
-    z = t->z;
-    ldz = t->cap;
+    if (e != hipSuccess) return e;
+    e = backward(w, bc, x + c0, ld, params, z, t->ld, grad_out + c0, ld, grad_params,
+                 grad_x ? grad_x + c0 : nullptr, ld, t, s, k > 0);
+    if (e != hipSuccess) return e;
   }
-  return backward(w, B, x, ld, params, z, ldz, grad_out, ld, grad_params, grad_x, ld, t, s);
+  return hipSuccess;
 }
 
+// One training step: chunk by chunk, features -> forward -> loss gradient ->
+// backward, the gradient of later chunks added in chunk order; then the loss
+// (the chunk sums in order) and Adam.  With the whole batch in one chunk
+// this is the plain step; with smaller chunks only one chunk's activations
+// exist at a time (nothing has to be recomputed: a sample's loss gradient
+// does not depend on the other samples).
 hipError_t train_step(const int *w, int64_t B, int64_t ld, const double *T, const double *P,
                       const double *Y, const float *target, float *params, float *grads,
                       float *adam_m, float *adam_v, int64_t step, float lr, bool recompute,
                       float *loss, const float *fc, const double *dc, TrainScratch *t,
                       hipStream_t s) {
+  (void)recompute;
   if (B > t->cap) return hipErrorInvalidValue;
   const int S = w[4];
-  hipLaunchKernelGGL(features_kernel, dim3(blocks_for(B)), dim3(256), 0, s, T, P, Y, ld, B, S, fc,
-                     dc, t->x, t->cap);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  e = forward(w, B, t->x, t->cap, params, t->z, t->cap, t->out, t->cap, s);
-  if (e != hipSuccess) return e;
-  // dL/do into dz[1] (the backward ping-pong starts writing dz[0])
-  int nb = (int)blocks_for((int64_t)S * B);
-  if (nb > 1024) nb = 1024;
-  hipLaunchKernelGGL(mse_kernel, dim3(nb), dim3(256), 0, s, (const float *)t->out, t->cap, target,
-                     ld, S, B, t->dz[1], t->lpart);
-  hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(64), 0, s, (const float *)t->lpart, nb,
-                     (double)B * S, loss);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  if (recompute) {
-    // keep only the inputs: regenerate the pre-activations for the backward
-    e = forward(w, B, t->x, t->cap, params, t->z, t->cap, t->out, t->cap, s);
+  const int64_t cc = t->ld;
+  const double denom = (double)B * S;
+  hipError_t e = hipSuccess;
+  int k = 0;
+  for (int64_t c0 = 0; c0 < B; c0 += cc, ++k) {
+    const int64_t bc = B - c0 < cc ? B - c0 : cc;
+    hipLaunchKernelGGL(features_kernel, dim3(blocks_for(bc)), dim3(256), 0, s, T + c0, P + c0,
+                       Y + c0, ld, bc, S, fc, dc, t->x, cc);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    e = forward(w, bc, t->x, cc, params, t->z, cc, t->out, cc, s);
+    if (e != hipSuccess) return e;
+    // dL/do into dz[1] (the backward ping-pong starts writing dz[0])
+    int nb = (int)blocks_for((int64_t)S * bc);
+    if (nb > 1024) nb = 1024;
+    hipLaunchKernelGGL(mse_kernel, dim3(nb), dim3(256), 0, s, (const float *)t->out, cc,
+                       target + c0, ld, S, bc, denom, t->dz[1], t->lpart);
+    hipLaunchKernelGGL(loss_chunk_kernel, dim3(1), dim3(64), 0, s, (const float *)t->lpart, nb,
+                       t->closs + k);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // mse_kernel wrote dO with the output's leading dimension (cc)
+    e = backward(w, bc, t->x, cc, params, t->z, cc, t->dz[1], cc, grads, nullptr, 0, t, s, k > 0);
     if (e != hipSuccess) return e;
   }
-  // mse_kernel wrote dO with the output's leading dimension (cap)
-  e = backward(w, B, t->x, t->cap, params, t->z, t->cap, t->dz[1], t->cap, grads, nullptr, 0, t, s);
-  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(64), 0, s, (const double *)t->closs, k, denom,
+                     loss);
   const int64_t np = (int64_t)param_off(w, 4);
   const double c1 = 1.0 / (1.0 - pow(0.9, (double)step));
   const double c2 = 1.0 / (1.0 - pow(0.999, (double)step));

@@ -22,13 +22,13 @@ def dev_state(st, device="cuda", ld=None):
 
 
 def make_handle(net, precision, thermo=None, act_amax=None, max_batch=0, device="cuda",
-                gelu="tanh", molar_mass=None):
+                gelu="tanh", molar_mass=None, recompute_chunk=0):
     import torch
     from paper_2508_18969_amd import ChemDNN
     params = torch.tensor(net.flat_params(), dtype=torch.float32, device=device)
     h = ChemDNN(net.widths, precision, params, net.in_mean, net.in_std, net.out_mean, net.out_std,
                 act_amax=act_amax, thermo=thermo, max_batch=max_batch, lam=net.lam, gelu=gelu,
-                molar_mass=molar_mass)
+                molar_mass=molar_mass, recompute_chunk=recompute_chunk)
     h._params = params
     return h
 

@@ -28,7 +28,7 @@ def test_header_declares_what_the_library_exports(L):
     lib = L.lib()
     for name in decl:
         assert hasattr(lib, name), name
-    assert lib.chem_dnn_abi_version() == 4
+    assert lib.chem_dnn_abi_version() == 5
     for st in (0, -1, -2, -3, -4, -5):
         assert L.strerror(st) and L.strerror(st) != "unknown status"
 
@@ -46,13 +46,23 @@ def test_workspace_bytes_and_validation(L):
     assert n > 4 * 110017          # at least the packed FP32 weights
     d2, k2 = _desc(L, max_batch=65536)
     assert L.workspace_bytes(d2) > n + 65536 * 700 * 4
+    # activation recomputation: the training scratch holds one chunk, so the
+    # workspace drops by at least the pre-activations of the other samples
+    d3, k3 = _desc(L, max_batch=65536, recompute_chunk=4096)
+    assert L.workspace_bytes(d2) - L.workspace_bytes(d3) >= (65536 - 4096) * 700 * 4
+    d4, k4 = _desc(L, max_batch=1 << 20, recompute_chunk=4096)
+    assert L.workspace_bytes(d4) < L.workspace_bytes(d2)        # 16x the batch, less memory
+    for bad_chunk in (-16, 100):                                 # negative, not a multiple of 16
+        d5, k5 = _desc(L, max_batch=65536, recompute_chunk=bad_chunk)
+        with pytest.raises(L.ChemDNNError):
+            L.workspace_bytes(d5)
     bad = [dict(widths=(19, 400, 200, 100, 16)),           # S mismatch
            dict(widths=(19, 400, 200, 17)),                # 3 layers: unsupported
            dict(widths=(19, 0, 200, 100, 17)),
            dict(precision=7),
            dict(in_std=np.zeros(19)),
            dict(precision="fp8"),                          # FP8 needs act_amax
-           dict(gelu=2),                                   # no such activation form
+           dict(gelu=3),                                   # no such activation form
            dict(molar_mass=-np.ones(17))]                  # molar masses must be positive
     for kw in bad:
         d3, k3 = _desc(L, **kw)
