@@ -33,7 +33,9 @@ import numpy as np
 from scipy import special
 
 SEED_BASE = 18969
-STREAMS = ("weights", "inputs", "calibration", "mechanism", "subsample", "extra")
+# (new names go at the end: a spawned child depends only on its index, so the
+# earlier streams keep their draws)
+STREAMS = ("weights", "inputs", "calibration", "mechanism", "subsample", "extra", "stats")
 
 # Network shapes of the five workloads.  D = S + 2 inputs (T, P, S species),
 # S outputs, three GELU hidden layers.
@@ -281,11 +283,14 @@ def uniform_state_input_moments(S: int, lam: float = BOXCOX_LAMBDA):
     return np.array(mean), np.array(std)
 
 
-def make_net(config: int, widths=None, bias_scale: float = 0.0) -> Net:
+def make_net(config: int, widths=None, bias_scale: float = 0.0, out_stats: bool = False) -> Net:
     """Random-init network of a workload with exact input Z-score statistics.
 
     Output statistics are the identity (mean 0, std 1): an untrained net's
-    raw output is taken as the normalised Box-Cox increment.
+    raw output is taken as the normalised Box-Cox increment.  With
+    ``out_stats`` they are drawn instead (a trained net's label statistics
+    stand-in): mean ~ U(-0.2, 0.2), std ~ U(0.5, 2), from the "stats" stream.
+    ``bias_scale`` > 0 draws every layer's biases from U(+-bias_scale).
     """
     if widths is None:
         widths = NET_SMALL if config in (1, 4) else NET_ODENET if config == 6 else NET_LARGE
@@ -293,7 +298,12 @@ def make_net(config: int, widths=None, bias_scale: float = 0.0) -> Net:
     W, b = xavier_weights(rng, widths, bias_scale)
     S = widths[-1]
     mu, sd = uniform_state_input_moments(S)
-    return Net(tuple(widths), W, b, mu, sd, np.zeros(S), np.ones(S))
+    om, osd = np.zeros(S), np.ones(S)
+    if out_stats:
+        r = streams(config)["stats"]
+        om = r.uniform(-0.2, 0.2, size=S)
+        osd = r.uniform(0.5, 2.0, size=S)
+    return Net(tuple(widths), W, b, mu, sd, om, osd)
 
 
 def make_state(config: int, n: int, stream: str = "inputs", S: int | None = None) -> State:

@@ -212,6 +212,80 @@ def test_gelu_table_bf16_matches_emulation():
     assert rg.max() <= 0.5 * re.max()
 
 
+def _table_boundary_cells(st, net, delta=2e-6):
+    """Cells with a hidden pre-activation (FP64 forward with the table)
+    within delta of an interval boundary -3 + 0.01 k of the table (or of its
+    ends): there the FP32 pre-activation may fall in the neighbouring
+    interval.  The FP16 table jumps at a boundary by up to its coefficient
+    rounding (about 1e-3), the FP32 table by about 1e-8."""
+    a = chem.features(st.T, st.P, st.Y, net.in_mean, net.in_std, net.lam)
+    near = np.zeros(st.n, bool)
+    for l, (W, b) in enumerate(zip(net.W, net.b)):
+        z = np.asarray(W, np.float64) @ a + np.asarray(b, np.float64)[:, None]
+        if l == len(net.W) - 1:
+            break
+        u = (z + 3.0) * 100.0
+        near |= np.any((np.abs(u - np.round(u)) < 100.0 * delta) & (np.abs(z) <= 3.0 + delta), axis=0)
+        a = chem.gelu_table16(z)
+    return near
+
+
+@pytest.mark.parametrize("config,n", [(1, 4096 - 3), (2, 2048 + 5)])
+def test_gelu_table16_fp32_matches_oracle(config, n):
+    """FP32 operands with the FP16-coefficient table (Sec. 3.3.2: FP16
+    tabulation) against the FP64 oracle evaluating the same FP16
+    coefficients.  The table is discontinuous at its interval boundaries by
+    up to the coefficient rounding (about 1e-3): a pre-activation that the
+    FP32 accumulation leaves within about 1e-7 of a boundary may take the
+    neighbouring interval's polynomial on one side.  So: 1e-5 relative on
+    every cell without a pre-activation within 2e-6 of a boundary; the
+    others (counted) must stay within the jump's effect, 1e-3 relative."""
+    _note(f"case gelu table16 fp32 config={config} n={n}")
+    net = synth.make_net(config)
+    S = 17 if config == 1 else 29
+    thermo = synth.make_thermo(config, S)
+    st = synth.make_state(config, n)
+    h = make_handle(net, "fp32", thermo=thermo, gelu="table16")
+    Yg, Tg, nbad = _run(h, st)
+    ref = chem.step(st.T, st.P, st.Y, net, thermo=thermo, act=chem.gelu_table16)
+    assert nbad == 0
+    near = _table_boundary_cells(st, net)
+    ok = ~near
+    e_y = rel_err(Yg[:, ok], ref["Y_new"][:, ok])
+    e_t = rel_err(Tg[ok], ref["T_new"][ok], floor=1.0)
+    e_near = rel_err(Yg[:, near], ref["Y_new"][:, near]) if near.any() else 0.0
+    exact = chem.step(st.T, st.P, st.Y, net, thermo=thermo)
+    _note(f"  {near.sum()} of {st.n} cells have a pre-activation near a table boundary (rel err Y "
+          f"{e_near:.2e}); the others: rel err Y {e_y:.3e}  T {e_t:.3e} | FP16 table vs tanh form "
+          f"(oracle): max abs dY {np.abs(ref['Y_new'] - exact['Y_new']).max():.2e}, "
+          f"dT {np.abs(ref['T_new'] - exact['T_new']).max():.2e} K")
+    assert e_y <= 1e-5
+    assert e_t <= 1e-5
+    assert e_near <= 1e-3
+
+
+def test_gelu_table16_bf16_matches_emulation():
+    """BF16 operands with the FP16-coefficient table against the emulation
+    with the same table; the statistical bar of the narrow formats."""
+    _note("case gelu table16 bf16 n=4096+11")
+    net = synth.make_net(2)
+    thermo = synth.make_thermo(2, 29)
+    st = synth.make_state(2, 4096 + 11)
+    h = make_handle(net, "bf16", thermo=thermo, gelu="table16")
+    Yg, Tg, _ = _run(h, st)
+    emu = chem.step(st.T, st.P, st.Y, net, fmt="bf16", thermo=thermo, act=chem.gelu_table16)
+    ex = chem.step(st.T, st.P, st.Y, net, thermo=thermo, act=chem.gelu_table16)
+    ge, ee = Yg - emu["Y_new"], emu["Y_new"] - ex["Y_new"]
+    rg, re = _rel(Yg, emu["Y_new"]), _rel(emu["Y_new"], ex["Y_new"])
+    rms_g, rms_e = np.sqrt(np.mean(ge ** 2)), np.sqrt(np.mean(ee ** 2))
+    _note(f"  gpu-emu: rms {rms_g:.2e} med {np.median(rg):.2e} max {rg.max():.2e} | "
+          f"emu-fp64: rms {rms_e:.2e} med {np.median(re):.2e} max {re.max():.2e}")
+    assert rms_g <= 0.25 * rms_e
+    assert np.median(rg) <= 0.05 * np.median(re)
+    assert np.quantile(rg, 0.99) <= 0.5 * np.quantile(re, 0.99)
+    assert rg.max() <= 0.5 * re.max()
+
+
 # ------------------------------------------------------------------ source terms
 @pytest.mark.parametrize("config,n", [(1, 4096 + 5), (2, 2053)])
 def test_source_terms_match_oracle(config, n):
