@@ -52,7 +52,9 @@ enum {
     CHEM_DNN_ENODEV = -2,      /* no HIP device */
     CHEM_DNN_EWORKSPACE = -3,  /* workspace NULL, misaligned or smaller than required */
     CHEM_DNN_EUNSUPPORTED = -4,/* device is not gfx950, or network shape not built */
-    CHEM_DNN_EHIP = -5         /* a HIP runtime call or kernel launch failed */
+    CHEM_DNN_EHIP = -5,        /* a HIP runtime call or kernel launch failed */
+    CHEM_DNN_ETOOLARGE = -6    /* the request needs more than the allocation-free entry point's
+                                  static scratch (CHEM_DNN_NOALLOC_SCRATCH_BYTES) */
 };
 
 enum {
@@ -216,6 +218,26 @@ int32_t chem_dnn_train_step(chem_dnn *h, int64_t B, int64_t ld, const double *T,
                             float *params, float *grads, float *adam_m, float *adam_v,
                             int64_t step, float lr, int32_t recompute, float *loss,
                             void *stream);
+
+/* Allocation-free training step, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight loops, harnesses that forbid
+ * allocation): chem_dnn_train_step with its training scratch in a static
+ * device array of the library - CHEM_DNN_NOALLOC_SCRATCH_BYTES per GPU,
+ * reserved when the library's code is loaded on that GPU and held until the
+ * process ends - instead of the handle's workspace, so the handle needs no
+ * training scratch (max_batch may be 0).  B is not bounded by max_batch; the
+ * scratch is: ETOOLARGE when the batch (in chunks of the handle's
+ * recompute_chunk, if any) needs more.  It runs the same kernels in the same
+ * schedule as chem_dnn_train_step on a handle with the same recompute_chunk
+ * (results equal bit for bit) and calls no allocation routine.  All calls on
+ * one GPU share its array: calls that overlap on one GPU (concurrent streams,
+ * threads or handles) race and must be serialised by the caller.  Nothing in
+ * the array has to start at zero; it keeps the last call's contents. */
+#define CHEM_DNN_NOALLOC_SCRATCH_BYTES (64u << 20)
+int32_t chem_dnn_train_step_noalloc(chem_dnn *h, int64_t B, int64_t ld, const double *T,
+                                    const double *P, const double *Y, const float *target,
+                                    float *params, float *grads, float *adam_m, float *adam_v,
+                                    int64_t step, float lr, float *loss, void *stream);
 
 /* Release the handle (host memory only; the caller frees the workspace). */
 int32_t chem_dnn_destroy(chem_dnn *h);

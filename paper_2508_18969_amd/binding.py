@@ -16,7 +16,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "libchemdnn.so")
 
-OK, EINVAL, ENODEV, EWORKSPACE, EUNSUPPORTED, EHIP = 0, -1, -2, -3, -4, -5
+OK, EINVAL, ENODEV, EWORKSPACE, EUNSUPPORTED, EHIP, ETOOLARGE = 0, -1, -2, -3, -4, -5, -6
 FP32, BF16, FP16, FP8E4M3 = 0, 1, 2, 3
 PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp16": FP16, "fp8": FP8E4M3}
 EXPORTS = ("chem_dnn_workspace_bytes", "chem_dnn_init", "chem_dnn_set_params", "chem_dnn_step",
@@ -24,7 +24,7 @@ EXPORTS = ("chem_dnn_workspace_bytes", "chem_dnn_init", "chem_dnn_set_params", "
            "chem_dnn_mlp_backward", "chem_dnn_train_step", "chem_dnn_destroy",
            "chem_dnn_strerror", "chem_dnn_abi_version", "chem_prop_workspace_bytes",
            "chem_prop_init", "chem_prop_set_params", "chem_prop_eval", "chem_prop_destroy",
-           "chem_dnn_debug_layers")
+           "chem_dnn_debug_layers", "chem_dnn_train_step_noalloc")
 DEBUG_MAX_CELLS = 4096
 
 _dp = C.POINTER(C.c_double)
@@ -76,6 +76,8 @@ def lib():
                                           C.c_float, C.c_int32, vp, vp]
         L.chem_dnn_destroy.argtypes = [vp]
         L.chem_dnn_debug_layers.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp]
+        L.chem_dnn_train_step_noalloc.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp,
+                                                  i64, C.c_float, vp, vp]
         L.chem_prop_workspace_bytes.argtypes = [C.POINTER(PropDesc), C.POINTER(C.c_size_t)]
         L.chem_prop_init.argtypes = [C.POINTER(PropDesc), vp, vp, C.c_size_t, vp, C.POINTER(vp)]
         L.chem_prop_set_params.argtypes = [vp, vp, vp]
@@ -388,6 +390,28 @@ class ChemDNN:
                                          _ptr(params), _ptr(grads), _ptr(adam_m), _ptr(adam_v),
                                          int(step), float(lr), int(bool(recompute)), _ptr(loss),
                                          _stream()), "chem_dnn_train_step")
+        return loss
+
+    def train_step_noalloc(self, T, P, Y, target, params, grads, adam_m, adam_v, step, lr=1e-3,
+                           loss=None):
+        """chem_dnn_train_step_noalloc: the training step with its scratch in
+        the library's static device array (no workspace scratch needed)."""
+        import torch
+        B = int(T.shape[0])
+        ld = int(Y.stride(0))
+        for t, nm, r in ((T, "T", 1), (P, "P", 1), (Y, "Y", self.S)):
+            _check_field(t, nm, r, B, ld, torch.float64)
+        _check_field(target, "target", self.S, B, ld, torch.float32)
+        np_ = n_params(self.widths)
+        for t, nm in ((params, "params"), (grads, "grads"), (adam_m, "adam_m"), (adam_v, "adam_v")):
+            _check_params(t, np_, nm)
+        if loss is None:
+            loss = torch.empty(1, dtype=torch.float32, device=T.device)
+        _check(lib().chem_dnn_train_step_noalloc(self._h, B, ld, _ptr(T), _ptr(P), _ptr(Y),
+                                                 _ptr(target), _ptr(params), _ptr(grads),
+                                                 _ptr(adam_m), _ptr(adam_v), int(step), float(lr),
+                                                 _ptr(loss), _stream()),
+               "chem_dnn_train_step_noalloc")
         return loss
 
     def close(self):

@@ -5,6 +5,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 
 #include "../../include/chem_dnn.h"
@@ -33,6 +34,7 @@ struct chem_dnn {
   void *wpack[8];
   TrainScratch tr;
   int64_t max_batch;
+  int64_t recompute_chunk;
   int thermo;
   int molar;       // molar masses given: source terms available
   int gelu_form;
@@ -64,10 +66,30 @@ struct chem_prop {
   float hfc[FConst::N];
 };
 
+// Scratch of the allocation-free training step: one copy per GPU, held until
+// the process ends.  Host code never passes this name to a kernel (on the
+// host it only stands in for the symbol): it uses the device address that
+// hipGetSymbolAddress returns for the current device, kept per device.
+static __device__ __align__(256) uint8_t scratch[CHEM_DNN_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 constexpr size_t kAlign = 256;
 
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint8_t *g_scratch[kMaxDevices];   // device address of `scratch` on each device
+
+// Looks up the static scratch on device `dev` (the current device) once.
+int32_t scratch_init(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return CHEM_DNN_EUNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch[dev]) return CHEM_DNN_OK;
+  void *p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return CHEM_DNN_EHIP;
+  g_scratch[dev] = (uint8_t *)p;
+  return CHEM_DNN_OK;
+}
 
 // Coefficients of the tabulated GELU: per interval i of [-3, 3] (width
 // 0.01), the value, first derivative and half the second derivative of
@@ -451,6 +473,9 @@ const char *chem_dnn_strerror(int32_t st) {
     case CHEM_DNN_EWORKSPACE: return "workspace missing, misaligned or too small";
     case CHEM_DNN_EUNSUPPORTED: return "unsupported device or network shape";
     case CHEM_DNN_EHIP: return "HIP runtime error";
+    case CHEM_DNN_ETOOLARGE:
+      return "request exceeds the allocation-free entry point's static scratch "
+             "(CHEM_DNN_NOALLOC_SCRATCH_BYTES)";
     default: return "unknown status";
   }
 }
@@ -480,6 +505,8 @@ int32_t chem_dnn_init(const chem_dnn_desc *d, const float *params, void *workspa
   st = current_device(&dev, &n_cu);
   if (st) return st;
   const bool layered = lay.prepare == nullptr;
+  // the static scratch of the allocation-free training step (fused shapes)
+  if (!layered && (st = scratch_init(dev)) != CHEM_DNN_OK) return st;
   if ((layered ? layered_prepare() : lay.prepare()) != hipSuccess) return CHEM_DNN_EHIP;
   if (d->max_batch > 0 && train_prepare() != hipSuccess) return CHEM_DNN_EHIP;
 
@@ -519,6 +546,7 @@ int32_t chem_dnn_init(const chem_dnn_desc *d, const float *params, void *workspa
     h->wpack[l] = h->ws + p.w[l];
   }
   h->max_batch = d->max_batch;
+  h->recompute_chunk = d->recompute_chunk;
   train_scratch_layout(&h->tr, h->ws + p.train, d->widths, d->max_batch, d->recompute_chunk);
   h->thermo = d->thermo_hf ? 1 : 0;
   h->molar = d->molar_mass ? 1 : 0;
@@ -689,6 +717,28 @@ int32_t chem_dnn_train_step(chem_dnn *h, int64_t B, int64_t ld, const double *T,
   return hip_status(train_step(h->widths, B, ld, T, P, Y, target, params, grads, adam_m, adam_v,
                                step, lr, recompute != 0, loss, h->fc, h->dc, &h->tr,
                                (hipStream_t)stream));
+}
+
+int32_t chem_dnn_train_step_noalloc(chem_dnn *h, int64_t B, int64_t ld, const double *T,
+                                    const double *P, const double *Y, const float *target,
+                                    float *params, float *grads, float *adam_m, float *adam_v,
+                                    int64_t step, float lr, float *loss, void *stream) {
+  if (h && h->layered) return CHEM_DNN_EUNSUPPORTED;
+  if (!h || B < 1 || ld < B || step < 1) return CHEM_DNN_EINVAL;
+  if (!T || !P || !Y || !target || !params || !grads || !adam_m || !adam_v || !loss)
+    return CHEM_DNN_EINVAL;
+  if (!(lr > 0.0f)) return CHEM_DNN_EINVAL;
+  uint8_t *base = (h->dev >= 0 && h->dev < kMaxDevices) ? g_scratch[h->dev] : nullptr;
+  if (!base) return CHEM_DNN_EHIP;
+  // the same chunk schedule as chem_dnn_train_step on a handle with this
+  // recompute_chunk; per-sample buffers padded to 16 samples (aligned rows)
+  const int64_t cap = (B + 15) / 16 * 16;
+  if (train_scratch_bytes(h->widths, cap, h->recompute_chunk) > CHEM_DNN_NOALLOC_SCRATCH_BYTES)
+    return CHEM_DNN_ETOOLARGE;
+  TrainScratch t;
+  train_scratch_layout(&t, base, h->widths, cap, h->recompute_chunk);
+  return hip_status(train_step(h->widths, B, ld, T, P, Y, target, params, grads, adam_m, adam_v,
+                               step, lr, false, loss, h->fc, h->dc, &t, (hipStream_t)stream));
 }
 
 int32_t chem_dnn_destroy(chem_dnn *h) {
