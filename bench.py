@@ -32,8 +32,15 @@ FLOP_PER_CELL = 2 * (31 * 1600 + 1600 * 800 + 800 * 400 + 400 * 29)     # 3,322,
 STATE_BYTES_PER_CELL = 8 * (2 + 29) + 8 * (29 + 1)                       # in + out, FP64
 PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp16": 2500.0, "fp8": 5000.0}
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ["paper_2508_18969_amd/csrc/step.hip", "paper_2508_18969_amd/csrc/common.h"]
+KERNEL_SOURCES = ["paper_2508_18969_amd/csrc/step_kernel.h", "paper_2508_18969_amd/csrc/step_bf16.hip",
+                  "paper_2508_18969_amd/csrc/common.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_chem_step_bf16_2p20.json")
+BLOCK_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_chem_step_block_2p27.json")
+
+
+def _log(msg):
+    """Progress on stderr (stdout carries only the result line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def kernel_sha():
@@ -55,14 +62,25 @@ def stored_traffic(n_cells):
     return float(t["hbm_bytes_per_launch"])
 
 
+def stored_block_traffic():
+    """HBM bytes per launch of the 512^3-block launches (per precision) from
+    the committed counter runs, if taken on the current kernel source."""
+    try:
+        t = json.load(open(BLOCK_TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return {}
+    return t if t.get("kernel_sha") == kernel_sha() else {}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cells", type=int, default=1 << 20)
-    ap.add_argument("--precisions", default="fp32,bf16,fp16,fp8,bf16+table",
-                    help="'+table' selects the tabulated GELU")
+    ap.add_argument("--precisions", default="fp32,bf16,fp16,fp8,bf16+table,fp16+table16",
+                    help="'+table' / '+table16' select the tabulated GELU with FP32 / FP16 "
+                         "coefficients")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline leg")
     ap.add_argument("--workloads",
                     default="fp8_bimodal_2p24,block_2p27,train_b65536,source_2p20,odenet_2p20,"
@@ -101,7 +119,7 @@ def main():
         base, _, form = prec.partition("+")
         return ChemDNN(net.widths, base, params, net.in_mean, net.in_std, net.out_mean,
                        net.out_std, act_amax=act_amax, thermo=thermo, lam=net.lam,
-                       gelu="table" if form == "table" else "tanh")
+                       gelu=form or "tanh")
 
     precs = [p for p in args.precisions.split(",") if p]
     results = {}
@@ -136,6 +154,7 @@ def main():
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / k
+        _log(f"{prec}: {ms:.3f} ms per step")
         outputs[prec] = (Yo[:, sample_t].cpu().numpy(), To[sample_t].cpu().numpy())
         tflops = FLOP_PER_CELL * n / (ms * 1e-3) * 1e-12
         results[prec] = {"ms_per_step": ms, "cells_per_s": n / (ms * 1e-3), "tflops": tflops,
@@ -177,6 +196,7 @@ def main():
     sampled = {}
     for wl in [w for w in args.workloads.split(",") if w]:
         extra[wl], sampled[wl] = WORKLOADS[wl](torch, synth, ChemDNN)
+        _log(f"workload {wl} done")
 
     cpu = None
     if not args.no_cpu:
@@ -259,7 +279,9 @@ def wl_fp8_bimodal(torch, synth, ChemDNN, n=1 << 24):
     idx_t = torch.tensor(idx, device=dev)
     Yo, To = torch.empty_like(Y), torch.empty_like(T)
     params = torch.tensor(net.flat_params(), device=dev)
-    out, samp = {}, {"state": (st.T[idx], st.P[idx], st.Y[:, idx]), "net": net, "thermo": thermo}
+    io = synth.subsample_indices(3, n, 1 << 16)
+    out, samp = {}, {"state": (st.T[idx], st.P[idx], st.Y[:, idx]), "net": net, "thermo": thermo,
+                     "oracle_state": (st.T[io], st.P[io], np.ascontiguousarray(st.Y[:, io]))}
     for prec in ("fp8", "bf16", "fp32"):
         h = ChemDNN(net.widths, prec, params, net.in_mean, net.in_std, net.out_mean, net.out_std,
                     act_amax=amax if prec == "fp8" else None, thermo=thermo, lam=net.lam)
@@ -289,8 +311,11 @@ def wl_block(torch, synth, ChemDNN, edge=512):
     amax = _fp8_amax(torch, ChemDNN, net, thermo, T[cal_t].contiguous(), P[cal_t].contiguous(),
                      Y[:, cal_t].contiguous())
     idx_t = torch.tensor(synth.subsample_indices(5, n, 1 << 10), device=dev)
+    io_t = torch.tensor(synth.subsample_indices(5, n, 1 << 16), device=dev)
     samp = {"state": (T[idx_t].cpu().numpy(), P[idx_t].cpu().numpy(), Y[:, idx_t].cpu().numpy()),
-            "net": net, "thermo": thermo}
+            "net": net, "thermo": thermo,
+            "oracle_state": (T[io_t].cpu().numpy(), P[io_t].cpu().numpy(),
+                             Y[:, io_t].contiguous().cpu().numpy())}
     Yo, To = torch.empty_like(Y), torch.empty_like(T)
     params = torch.tensor(net.flat_params(), device=dev)
     out = {}
@@ -300,6 +325,9 @@ def wl_block(torch, synth, ChemDNN, edge=512):
         ms = _time_steps(torch, h, T, P, Y, Yo, To, 3, 1)
         h.close()
         out[prec] = _rate(n, ms, prec)
+        tr = stored_block_traffic().get(prec)
+        # HBM bytes counted by FETCH_SIZE / WRITE_SIZE for this launch, per second
+        out[prec]["hbm_GBps"] = tr["hbm_bytes_per_launch"] / (ms * 1e-3) * 1e-9 if tr else None
         samp[prec] = (Yo[:, idx_t].cpu().numpy(), To[idx_t].cpu().numpy())
     out["config"] = {"cells": n, "block": f"{edge}^3", "T": "300 + 2900 c K", "P": "5 + 15 p MPa",
                      "Y": "mix of LOX-like / CH4-like compositions and Dirichlet(0.5)"}
@@ -308,39 +336,43 @@ def wl_block(torch, synth, ChemDNN, edge=512):
     return out, samp
 
 
-def wl_train(torch, synth, ChemDNN, B=65536, steps=20):
+def wl_train(torch, synth, ChemDNN, B=65536, steps=20, chunk=8192):
     """One Adam training step of the 19-400-200-100-17 net over a batch of
-    65,536 states (features, FP32 forward with saved pre-activations, MSE,
-    backward, Adam), timed; targets are seeded normal draws (the step's work
-    does not depend on their values)."""
+    65,536 states (features, FP32 forward, MSE, backward, Adam), timed with
+    the pre-activations of the whole batch saved, and with activation
+    recomputation in chunks of 8,192 samples (forward and backward chunk by
+    chunk, gradient accumulated; the workspace holds one chunk's
+    pre-activations); targets are seeded normal draws (the step's work does
+    not depend on their values)."""
     net = synth.make_net(4)
     st = synth.make_state(4, B)
     dev = torch.device("cuda")
     T, P, Y = (torch.tensor(a, device=dev) for a in (st.T, st.P, st.Y))
     rng = synth.streams(4)["extra"]
     tgt = torch.tensor(rng.standard_normal((17, B)), dtype=torch.float32, device=dev)
-    p = torch.tensor(net.flat_params(), device=dev)
-    g, m, v = torch.empty_like(p), torch.zeros_like(p), torch.zeros_like(p)
-    h = ChemDNN(net.widths, "fp32", p, net.in_mean, net.in_std, net.out_mean, net.out_std,
-                lam=net.lam, max_batch=B)
+    p0 = torch.tensor(net.flat_params(), device=dev)
     out = {}
-    for recompute in (False, True):
+    for name, rc in (("saved", 0), (f"recompute_chunk_{chunk}", chunk)):
+        p = p0.clone()
+        g, m, v = torch.empty_like(p), torch.zeros_like(p), torch.zeros_like(p)
+        h = ChemDNN(net.widths, "fp32", p, net.in_mean, net.in_std, net.out_mean, net.out_std,
+                    lam=net.lam, max_batch=B, recompute_chunk=rc)
         for k in range(1, 3):
-            h.train_step(T, P, Y, tgt, p, g, m, v, k, lr=1e-3, recompute=recompute)
+            h.train_step(T, P, Y, tgt, p, g, m, v, k, lr=1e-3)
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record()
         for k in range(3, 3 + steps):
-            h.train_step(T, P, Y, tgt, p, g, m, v, k, lr=1e-3, recompute=recompute)
+            h.train_step(T, P, Y, tgt, p, g, m, v, k, lr=1e-3)
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps
         fl = 3 * 2 * sum(a * b for a, b in zip(net.widths[:-1], net.widths[1:])) * B
-        out["recompute" if recompute else "saved"] = {
-            "ms_per_step": ms, "samples_per_s": B / (ms * 1e-3),
-            "tflops_fwd_bwd": fl / (ms * 1e-3) * 1e-12}
-    h.close()
+        out[name] = {"ms_per_step": ms, "samples_per_s": B / (ms * 1e-3),
+                     "tflops_fwd_bwd": fl / (ms * 1e-3) * 1e-12,
+                     "workspace_bytes": int(h.workspace.numel())}
+        h.close()
     out["torch_reference"] = _torch_train_step_ms(torch, net.widths, B, steps)
     out["config"] = {"batch": B, "widths": list(net.widths), "optimizer": "Adam lr 1e-3",
                      "targets": "seeded normal draws of the label shape"}
@@ -543,14 +575,21 @@ WORKLOADS = {"fp8_bimodal_2p24": wl_fp8_bimodal, "block_2p27": wl_block, "train_
 
 
 def _counter_means(path, name_part):
-    """Mean of each counter over the dispatches whose kernel name contains
-    name_part (rocprofv3 counter_collection CSV, values in KiB)."""
+    """Mean of each counter over the dispatches of the headline kernel (BF16
+    operands, tanh GELU) at the headline size: kernel names containing
+    name_part, values within 4x of the smallest (larger launches of the same
+    kernel, e.g. the 512^3 block, are left out; rocprofv3 counter_collection
+    CSV, values in KiB)."""
     import csv
     acc = {}
     for r in csv.DictReader(open(path)):
         if name_part in r["Kernel_Name"]:
             acc.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
-    return {k: sum(v) / len(v) for k, v in acc.items()}
+    out = {}
+    for k, v in acc.items():
+        sel = [x for x in v if x <= 4 * min(v)]
+        out[k] = sum(sel) / len(sel)
+    return out
 
 
 def write_traffic(fetch_csv, write_csv, n_cells, copy_bytes):
@@ -559,14 +598,15 @@ def write_traffic(fetch_csv, write_csv, n_cells, copy_bytes):
     reads and writes copy_bytes each)."""
     if copy_bytes <= 0:
         sys.exit("--traffic needs --copy-probe BYTES of the counter runs")
-    f_k = _counter_means(fetch_csv, "chem_step")["FETCH_SIZE"]
-    w_k = _counter_means(write_csv, "chem_step")["WRITE_SIZE"]
-    # the copy is the largest other dispatch of the run
+    kern = "chem_step_kernel<chemdnn::Cfg<chemdnn::OpBF16, 4, 4, 1600, 800, 400>, false, 0,"
+    f_k = _counter_means(fetch_csv, kern)["FETCH_SIZE"]
+    w_k = _counter_means(write_csv, kern)["WRITE_SIZE"]
+    # the probe is the largest plain copy of the run
     import csv
     f_c = max(float(r["Counter_Value"]) for r in csv.DictReader(open(fetch_csv))
-              if "chem_step" not in r["Kernel_Name"] and r["Counter_Name"] == "FETCH_SIZE")
+              if "copyBuffer" in r["Kernel_Name"] and r["Counter_Name"] == "FETCH_SIZE")
     w_c = max(float(r["Counter_Value"]) for r in csv.DictReader(open(write_csv))
-              if "chem_step" not in r["Kernel_Name"] and r["Counter_Name"] == "WRITE_SIZE")
+              if "copyBuffer" in r["Kernel_Name"] and r["Counter_Name"] == "WRITE_SIZE")
     fs, ws = copy_bytes / f_c, copy_bytes / w_c
     rec = {"kernel_sha": kernel_sha(), "cells": n_cells,
            "fetch_kib_per_launch": f_k, "write_kib_per_launch": w_k,
@@ -579,22 +619,32 @@ def write_traffic(fetch_csv, write_csv, n_cells, copy_bytes):
     print(json.dumps(rec))
 
 
-def cpu_baseline(st, net, thermo, sample, outputs, results, sampled=None, extra=None):
-    """The FP64 oracle on the host cores, on a bounded sample of the same
-    workload; its results are also the reference of the stated errors (of the
-    headline workload and, on their own samples, of the further workloads)."""
-    from threadpoolctl import threadpool_info
-    from oracle import chem
+def _median_s(f, reps=3, warm=None):
+    """Median wall time of `reps` calls of f, after one untimed call of warm
+    (a smaller instance of the same work; f itself if None)."""
+    (warm or f)()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        f()
+        ts.append(time.perf_counter() - t0)
+    return float(np.median(ts))
+
+
+def cpu_baseline(st, net, thermo, sample, outputs, results, sampled=None, extra=None,
+                 n_oracle=1 << 16):
+    """The FP64 oracle on the host cores: the headline workload on a seeded
+    2^16-cell subsample (median of 3 after a warm-up), and beside it the
+    4096-cell 17-species step, the training step at batch 65,536 and 2^16-cell
+    subsamples of the 2^24-cell bimodal and the 512^3 block workloads.  Its
+    results on the error samples are also the reference of the stated errors
+    (of the headline workload and, on their own samples, of the further
+    workloads)."""
+    import synth
+    from threadpoolctl import threadpool_info, threadpool_limits
+    from oracle import chem, train
     idx = np.asarray(sample)
-    Ts, Ps, Ys = st.T[idx], st.P[idx], st.Y[:, idx]
-    ref = chem.step(Ts, Ps, Ys, net, thermo=thermo)           # warm-up, also the reference
-    reps, t0 = 0, time.perf_counter()
-    while True:
-        chem.step(Ts, Ps, Ys, net, thermo=thermo)
-        reps += 1
-        el = time.perf_counter() - t0
-        if el >= 10.0 or reps >= 200:
-            break
+    ref = chem.step(st.T[idx], st.P[idx], st.Y[:, idx], net, thermo=thermo)
     for prec, (Yg, Tg) in outputs.items():
         results[prec]["max_abs_dY"] = float(np.max(np.abs(Yg - ref["Y_new"])))
         results[prec]["max_abs_dT_K"] = float(np.max(np.abs(Tg - ref["T_new"])))
@@ -604,24 +654,56 @@ def cpu_baseline(st, net, thermo, sample, outputs, results, sampled=None, extra=
         Tw, Pw, Yw = sm["state"]
         refw = chem.step(Tw, Pw, Yw, sm["net"], thermo=sm["thermo"])
         for prec, val in sm.items():
-            if prec in ("state", "net", "thermo"):
+            if prec in ("state", "net", "thermo", "oracle_state"):
                 continue
             extra[wl][prec]["max_abs_dY"] = float(np.max(np.abs(val[0] - refw["Y_new"])))
             extra[wl][prec]["max_abs_dT_K"] = float(np.max(np.abs(val[1] - refw["T_new"])))
             extra[wl][prec]["error_sample_cells"] = int(len(Tw))
     threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
-    # the same oracle on one thread, on the first 1024 cells of the sample
-    from threadpoolctl import threadpool_limits
-    i1 = idx[:1024]
+
+    # headline: 2^16 seeded cells of the same workload
+    io = synth.subsample_indices(2, len(st.T), n_oracle)
+    To_, Po_, Yo_ = st.T[io], st.P[io], np.ascontiguousarray(st.Y[:, io])
+    _log("oracle timings on the host")
+    sec = _median_s(lambda: chem.step(To_, Po_, Yo_, net, thermo=thermo),
+                    warm=lambda: chem.step(To_[:1024], Po_[:1024], Yo_[:, :1024], net,
+                                           thermo=thermo))
+    # the same oracle on one thread, on 1024 cells of that subsample
     with threadpool_limits(limits=1):
         t1 = time.perf_counter()
-        chem.step(st.T[i1], st.P[i1], st.Y[:, i1], net, thermo=thermo)
-        one = len(i1) / (time.perf_counter() - t1)
-    return {"value": reps * len(idx) / el, "unit": "cells/s", "cores": int(threads),
+        chem.step(To_[:1024], Po_[:1024], Yo_[:, :1024], net, thermo=thermo)
+        one = 1024 / (time.perf_counter() - t1)
+    others = {}
+    # 4096 cells, 17 species, 19-400-200-100-17 (all cells)
+    net1, th1, st1 = synth.make_net(1), synth.make_thermo(1, 17), synth.make_state(1, 4096)
+    s1 = _median_s(lambda: chem.step(st1.T, st1.P, st1.Y, net1, thermo=th1))
+    others["step_4096_17sp"] = {"cells_per_s": 4096 / s1, "median_s": s1, "cells": 4096}
+    # one Adam step of the 19-400-200-100-17 net at batch 65,536
+    net4, st4 = synth.make_net(4), synth.make_state(4, 65536)
+    x4 = chem.features(st4.T, st4.P, st4.Y, net4.in_mean, net4.in_std, net4.lam)
+    t4 = synth.streams(4)["extra"].standard_normal((17, 65536))
+    q4 = net4.flat_params().astype(np.float64)
+    z4 = np.zeros_like(q4)
+    s4 = _median_s(lambda: train.train_step(x4, t4, q4, z4, z4, 1, list(net4.widths)),
+                   warm=lambda: train.train_step(x4[:, :4096], t4[:, :4096], q4, z4, z4, 1,
+                                                 list(net4.widths)))
+    others["train_step_b65536"] = {"samples_per_s": 65536 / s4, "median_s": s4, "batch": 65536}
+    # 2^16-cell subsamples of the larger workloads
+    for wl in ("fp8_bimodal_2p24", "block_2p27"):
+        sm = (sampled or {}).get(wl)
+        if not sm or "oracle_state" not in sm:
+            continue
+        Tw, Pw, Yw = sm["oracle_state"]
+        sw = _median_s(lambda: chem.step(Tw, Pw, Yw, sm["net"], thermo=sm["thermo"]),
+                       warm=lambda: chem.step(Tw[:1024], Pw[:1024], Yw[:, :1024], sm["net"],
+                                              thermo=sm["thermo"]))
+        others[wl] = {"cells_per_s": len(Tw) / sw, "median_s": sw, "cells": int(len(Tw))}
+        _log(f"oracle {wl}: {sw:.2f} s")
+    return {"value": len(io) / sec, "unit": "cells/s", "cores": int(threads),
             "kind": "oracle",
-            "sample": f"{len(idx)} seeded cells of the same workload, FP64 numpy oracle "
-                      f"(BLAS matmul), {reps} repetitions in {el:.1f} s",
-            "single_thread_value": one}
+            "sample": f"{len(io)} seeded cells of the same workload, FP64 numpy oracle "
+                      f"(BLAS matmul), median of 3 runs after a warm-up ({sec:.2f} s each)",
+            "single_thread_value": one, "workloads": others}
 
 
 if __name__ == "__main__":
