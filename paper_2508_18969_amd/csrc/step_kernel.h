@@ -324,15 +324,17 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
     f4 acc1[C::RB1W][CB];
     f4 y1[C::RB1W][CB];
     int wo = w;                                        // opaque copy, renewed per k-step
-    auto layer1_mma = [&](int sc, const frag_t (&w1f)[C::NW1]) {
+    // the layer-1 input fragments, re-read per chunk (cheaper than keeping
+    // them live through the layer-2 loop)
+    auto layer1_in = [&](frag_t (&a0)[C::NQ1][CB]) {
       if (!l1wave) return;
-      // the input fragments, re-read per chunk (cheaper than keeping them
-      // live through the layer-2 loop)
-      frag_t a0[C::NQ1][CB];
 #pragma unroll
       for (int q = 0; q < C::NQ1; ++q)
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) a0[q][cb] = lds_frag<frag_t>(A0, q * CB + cb, lane);
+    };
+    auto layer1_mma = [&](int sc, const frag_t (&w1f)[C::NW1], const frag_t (&a0)[C::NQ1][CB]) {
+      if (!l1wave) return;
 #pragma unroll
       for (int ii = 0; ii < C::RB1W; ++ii) {
         const f4 bias = *(const f4 *)(B1 + 16 * (sc * (C::SC / 16) + wo * C::RB1W + ii) + 4 * g);
@@ -473,8 +475,10 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
           w1r[ii * C::NQ1 + q] = ldb_frag<frag_t>(W1, rb * C::NQ1 + q, voff);
         }
     };
+    frag_t a0[C::NQ1][CB];
     w1_load(0);
-    layer1_mma(0, w1r);
+    layer1_in(a0);
+    layer1_mma(0, w1r, a0);
     layer1_act(0, 0, 0, NV1);
     w1_load(1);
 #pragma unroll
@@ -493,17 +497,22 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
       const int nbuf = (sc + 1) & 1;
       const int sv = opaque_v((sc & 1) * C::QSC * C::QBYTES + lane * FRAG);
       const int wa = opaque(w);
-      // the chunk's activation fragments, read once (constant offsets first,
-      // so that they land in the instructions' offset fields)
+      // The chunk's activation fragments, read once (constant offsets first,
+      // so that they land in the instructions' offset fields).  Only the
+      // first k-step's fragments and the layer-1 inputs are read before the
+      // first products: every wave reads the same fragments at the same time
+      // here, and the later k-steps' reads go out behind the first products
+      // instead of delaying them.
       frag_t act[C::QSC][NA2];
-#pragma unroll
-      for (int ql = 0; ql < C::QSC; ++ql) {
+      auto act_load = [&](int ql) {
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) act[ql][cb] = *(const frag_t *)((A1 + (ql * CB + cb) * 64 * FRAG) + sv);
 #pragma unroll
         for (int k = 0; k < S2::NREM; ++k)
           act[ql][CB + k] = *(const frag_t *)((A1 + ql * CB * 64 * FRAG) + (sv + S2::rem_cb(wa, k) * 64 * FRAG));
-      }
+      };
+      act_load(0);
+      layer1_in(a0);
 #pragma unroll
       for (int ql = 0; ql < C::QSC; ++ql) {
         const int q = sc * C::QSC + ql;
@@ -524,7 +533,9 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
           w2_load(wc[i], i, q + NB2);
           const int gi = ql * NW2 + i;                 // fragment group of the chunk
           if (gi == 0) {
-            layer1_mma(nsc, w1r);
+            layer1_mma(nsc, w1r, a0);
+#pragma unroll
+            for (int ql = 1; ql < C::QSC; ++ql) act_load(ql);
             w1_load(sc + 2);
             if constexpr (!STAGED) layer1_act(nsc, nbuf, 0, NV1);
           }
