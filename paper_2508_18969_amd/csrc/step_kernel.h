@@ -68,6 +68,11 @@ template <class Op_, int CB_, int NW_, int H1_, int H2_, int H3_> struct Cfg {
   using S3 = Split<R3, CB_, NW_>;
   static constexpr int QBYTES = CB * 64 * FRAG;     // one k-step of a tile's activations
   static constexpr int NW1 = RB1W * NQ1;             // layer-1 fragments per wave per chunk
+  // A chunk's layer-1 tiles: SC / 16 / RB1W row groups x CB cell-blocks.  With
+  // more waves than row groups, the waves of a row group split its
+  // cell-blocks (CBW each).
+  static constexpr int L1G = SC / 16 / RB1W;
+  static constexpr int CBW = NW_ > L1G ? CB_ * L1G / NW_ : CB_;
   static constexpr int NBIAS = H1P + H2N + H3N + 32; // biases of all layers, FP32
   static constexpr int LDS_BIAS = 0;
   static constexpr int LDS_DC = roundup(NBIAS * 4, 16);          // DConst or PConst block (FP64)
@@ -76,7 +81,7 @@ template <class Op_, int CB_, int NW_, int H1_, int H2_, int H3_> struct Cfg {
   static constexpr int LDS_A1 = LDS_A0 + NQ1 * QBYTES;
   static constexpr int LDS_A2 = LDS_A1 + 2 * QSC * QBYTES;
   static constexpr int NW2 = S2::F + S2::NREM;               // layer-2 fragments per wave per k-step
-  static constexpr int NB2 = QSC % 2 == 0 ? 2 : 1;           // layer-2 register buffers
+  static constexpr int NB2 = NW_ > 4 ? 1 : QSC % 2 == 0 ? 2 : 1;   // layer-2 register buffers
   static constexpr int A2_BYTES = Max<NQ3, NQ4>::v * QBYTES;
   // The LDS tail holds the GELU table (tabulated form only), then the
   // output-layer weights, copied once per workgroup when they fit.
@@ -317,32 +322,35 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
     // activation of values [v0, v1) (bias + GELU + quantise into A1 buffer
     // `buf`).  Value v of the chunk is output value v % 4 of tile v / 4:
     // row-block v / (4 CB) of this wave, cell-block (v / 4) % CB.
-    constexpr int NV1 = C::RB1W * CB * 4;              // activation values per lane per chunk
-    // layer 1 is computed by the first L1W waves (one chunk has SC / 16 row-blocks)
-    constexpr int L1W = C::SC / 16 / C::RB1W;
+    // Wave w computes row group w / NCG of the chunk, cell-blocks
+    // CBW (w % NCG) .. + CBW - 1.
+    constexpr int CBW = C::CBW, NCG = CB / CBW;
+    constexpr int NV1 = C::RB1W * CBW * 4;             // activation values per lane per chunk
+    // layer 1 is computed by the first L1W waves
+    constexpr int L1W = C::L1G * NCG;
     const bool l1wave = C::NW == L1W || w < L1W;
-    f4 acc1[C::RB1W][CB];
-    f4 y1[C::RB1W][CB];
+    f4 acc1[C::RB1W][CBW];
+    f4 y1[C::RB1W][CBW];
     int wo = w;                                        // opaque copy, renewed per k-step
     // the layer-1 input fragments, re-read per chunk (cheaper than keeping
     // them live through the layer-2 loop)
-    auto layer1_in = [&](frag_t (&a0)[C::NQ1][CB]) {
+    auto layer1_in = [&](frag_t (&a0)[C::NQ1][CBW]) {
       if (!l1wave) return;
 #pragma unroll
       for (int q = 0; q < C::NQ1; ++q)
 #pragma unroll
-        for (int cb = 0; cb < CB; ++cb) a0[q][cb] = lds_frag<frag_t>(A0, q * CB + cb, lane);
+        for (int c = 0; c < CBW; ++c) a0[q][c] = lds_frag<frag_t>(A0, q * CB + (wo % NCG) * CBW + c, lane);
     };
-    auto layer1_mma = [&](int sc, const frag_t (&w1f)[C::NW1], const frag_t (&a0)[C::NQ1][CB]) {
+    auto layer1_mma = [&](int sc, const frag_t (&w1f)[C::NW1], const frag_t (&a0)[C::NQ1][CBW]) {
       if (!l1wave) return;
 #pragma unroll
       for (int ii = 0; ii < C::RB1W; ++ii) {
-        const f4 bias = *(const f4 *)(B1 + 16 * (sc * (C::SC / 16) + wo * C::RB1W + ii) + 4 * g);
+        const f4 bias = *(const f4 *)(B1 + 16 * (sc * (C::SC / 16) + (wo / NCG) * C::RB1W + ii) + 4 * g);
 #pragma unroll
-        for (int cb = 0; cb < CB; ++cb) {
-          acc1[ii][cb] = Op::SCALED ? f4{0.f, 0.f, 0.f, 0.f} : bias;
+        for (int c = 0; c < CBW; ++c) {
+          acc1[ii][c] = Op::SCALED ? f4{0.f, 0.f, 0.f, 0.f} : bias;
 #pragma unroll
-          for (int q = 0; q < C::NQ1; ++q) acc1[ii][cb] = Op::mma(w1f[ii * C::NQ1 + q], a0[q][cb], acc1[ii][cb]);
+          for (int q = 0; q < C::NQ1; ++q) acc1[ii][c] = Op::mma(w1f[ii * C::NQ1 + q], a0[q][c], acc1[ii][c]);
         }
       }
     };
@@ -353,15 +361,16 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
 #pragma unroll
       for (int v = 0; v < NV1; ++v) {
         if (v < v0 || v >= v1) continue;
-        const int ii = v / (4 * CB), cb = (v / 4) % CB, r = v % 4;
-        const int rbl = wo * C::RB1W + ii;             // row-block within the chunk
+        const int ii = v / (4 * CBW), c = (v / 4) % CBW, r = v % 4;
+        const int cb = (wo % NCG) * CBW + c;
+        const int rbl = (wo / NCG) * C::RB1W + ii;     // row-block within the chunk
         const int rb = sc * (C::SC / 16) + rbl;
         const float bias = B1[16 * rb + 4 * g + r];
-        const float zz = Op::SCALED ? __builtin_fmaf(acc1[ii][cb][r], sout[0], bias) : acc1[ii][cb][r];
-        if constexpr (DBG) dbg_put(a.dbg_acc, a.dbg_acc_row[0], 16 * rb + 4 * g + r, C::H1, cell0 + 16 * cb + cl, acc1[ii][cb][r]);
-        y1[ii][cb][r] = act(zz);
+        const float zz = Op::SCALED ? __builtin_fmaf(acc1[ii][c][r], sout[0], bias) : acc1[ii][c][r];
+        if constexpr (DBG) dbg_put(a.dbg_acc, a.dbg_acc_row[0], 16 * rb + 4 * g + r, C::H1, cell0 + 16 * cb + cl, acc1[ii][c][r]);
+        y1[ii][c][r] = act(zz);
         if (r == 3) {
-          f4 y = y1[ii][cb];
+          f4 y = y1[ii][c];
           if (CALIB && cell0 + 16 * cb + cl < a.n)
 #pragma unroll
             for (int k = 0; k < 4; ++k) amx[1] = umaxf(amx[1], __builtin_fabsf(y[k]));
@@ -393,17 +402,19 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
       for (int k = 0; k < NOPS1; ++k) {
         if (k < k0 || k >= k1) continue;
         const int st = k / NV1, v = k % NV1;
-        const int ii = v / (4 * CB), cb = (v / 4) % CB, r = v % 4;
+        const int ii = v / (4 * CBW), c = (v / 4) % CBW, r = v % 4;
+        const int cb = (wo % NCG) * CBW + c;
+        const int rbl = (wo / NCG) * C::RB1W + ii;     // row-block within the chunk
         if (st == 0) {
           if constexpr (Op::SCALED) {
-            const float bias = B1[16 * (sc * (C::SC / 16) + wo * C::RB1W + ii) + 4 * g + r];
-            xs[v] = __builtin_fmaf(acc1[ii][cb][r], sout[0], bias);
+            const float bias = B1[16 * (sc * (C::SC / 16) + rbl) + 4 * g + r];
+            xs[v] = __builtin_fmaf(acc1[ii][c][r], sout[0], bias);
           } else {
-            xs[v] = acc1[ii][cb][r];
+            xs[v] = acc1[ii][c][r];
           }
           if constexpr (DBG)
-            dbg_put(a.dbg_acc, a.dbg_acc_row[0], 16 * (sc * (C::SC / 16) + wo * C::RB1W + ii) + 4 * g + r,
-                    C::H1, cell0 + 16 * cb + cl, acc1[ii][cb][r]);
+            dbg_put(a.dbg_acc, a.dbg_acc_row[0], 16 * (sc * (C::SC / 16) + rbl) + 4 * g + r,
+                    C::H1, cell0 + 16 * cb + cl, acc1[ii][c][r]);
           ts[v] = xs[v] * xs[v];
         } else if (st == 1) {
           ts[v] = __builtin_fmaf(ts[v], kG3, kG1);
@@ -423,7 +434,6 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
 #pragma unroll
             for (int j = 0; j < 4; ++j) amx[1] = umaxf(amx[1], __builtin_fabsf(y[j]));
           if (Op::SCALED) y *= inv_sa[1];
-          const int rbl = wo * C::RB1W + ii;
           if constexpr (DBG)
 #pragma unroll
             for (int k = 0; k < 4; ++k)
@@ -471,11 +481,11 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
       for (int ii = 0; ii < C::RB1W; ++ii)
 #pragma unroll
         for (int q = 0; q < C::NQ1; ++q) {
-          const int rb = cs * (C::SC / 16) + wo * C::RB1W + ii;
+          const int rb = cs * (C::SC / 16) + (wo / NCG) * C::RB1W + ii;
           w1r[ii * C::NQ1 + q] = ldb_frag<frag_t>(W1, rb * C::NQ1 + q, voff);
         }
     };
-    frag_t a0[C::NQ1][CB];
+    frag_t a0[C::NQ1][CBW];
     w1_load(0);
     layer1_in(a0);
     layer1_mma(0, w1r, a0);
