@@ -11,7 +11,7 @@ bool find_layout_fp8(int h1, int h2, int h3, NetLayout *out) {
     return true;
   }
   if (h1 == 1600 && h2 == 800 && h3 == 400) {
-    fill_layout<Cfg<OpF8, 3, 4, 1600, 800, 400>, false>(out);
+    fill_layout<Cfg<OpF8, 4, 8, 1600, 800, 400>, false>(out);
     return true;
   }
   return false;

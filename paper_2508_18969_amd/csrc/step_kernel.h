@@ -59,7 +59,7 @@ template <class Op_, int CB_, int NW_, int H1_, int H2_, int H3_> struct Cfg {
   // layers 2 and 3 compute H2N / H3N rows; as the next layer's input they
   // are zero-padded to whole k-steps (H2P / H3P)
   // FP8 fragments take twice the registers: no leftover tiles there
-  static constexpr int H2N = padN(H2_, CB_, FRAG == 32, NW_), H3N = padN(H3_, CB_, FRAG == 32, NW_);
+  static constexpr int H2N = padN(H2_, CB_, FRAG == 32 && NW_ <= 4, NW_), H3N = padN(H3_, CB_, FRAG == 32 && NW_ <= 4, NW_);
   static constexpr int H2P = roundup(H2N, KS), H3P = roundup(H3N, KS);
   static constexpr int R1 = H1P / 16, R2 = H2N / 16, R3 = H3N / 16, R4 = 2;
   static constexpr int NQ2 = H1P / KS, NQ3 = H2P / KS, NQ4 = H3P / KS;
