@@ -31,6 +31,7 @@ typedef int i4 __attribute__((ext_vector_type(4)));
 typedef int i8v __attribute__((ext_vector_type(8)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef double double2v __attribute__((ext_vector_type(2)));
 
 // tanh-form GELU, 0.5 x (1 + tanh(v)), v = sqrt(2/pi)(x + 0.044715 x^3),
 // evaluated as x / (1 + 2^(-2 v log2 e)) (the identity 0.5(1 + tanh v) =

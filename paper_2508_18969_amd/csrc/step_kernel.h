@@ -77,9 +77,16 @@ template <class Op_, int CB_, int NW_, int H1_, int H2_, int H3_> struct Cfg {
   static constexpr int LDS_BIAS = 0;
   static constexpr int LDS_DC = roundup(NBIAS * 4, 16);          // DConst or PConst block (FP64)
   static constexpr int LDS_FC = LDS_DC + Max<DConst::N, PConst::N>::v * 8;   // FConst block (FP32)
-  static constexpr int LDS_A0 = roundup(LDS_FC + FConst::N * 4, 256);
+  // The FP64 state of the tile (8 values per lane of the CB preprocess
+  // waves), kept from the preprocess for the post-processing.
+  static constexpr int ST_BYTES = CB * 64 * 8 * 8;
+  static constexpr int LDS_ST = roundup(LDS_FC + FConst::N * 4, 256);
+  static constexpr int LDS_A0 = roundup(LDS_ST + ST_BYTES, 256);
   static constexpr int LDS_A1 = LDS_A0 + NQ1 * QBYTES;
-  static constexpr int LDS_A2 = LDS_A1 + 2 * QSC * QBYTES;
+  // A2 (layers 3 and 4 inputs) shares the space of A0 and A1 (layers 1 and 2
+  // inputs): they are never in use at the same time
+  static constexpr int LDS_A2 = LDS_A0;
+  static constexpr int A01_BYTES = NQ1 * QBYTES + 2 * QSC * QBYTES;
   static constexpr int NW2 = S2::F + S2::NREM;               // layer-2 fragments per wave per k-step
   static constexpr int NB2 = NW_ > 4 ? 1 : QSC % 2 == 0 ? 2 : 1;   // layer-2 register buffers
   static constexpr int A2_BYTES = Max<NQ3, NQ4>::v * QBYTES;
@@ -92,7 +99,7 @@ template <class Op_, int CB_, int NW_, int H1_, int H2_, int H3_> struct Cfg {
   }
   // gt: 0 tanh form, 1 FP32 table (16 bytes per interval), 2 FP16 table (8)
   static constexpr int tab_bytes(int gt) { return gt == 1 ? GTAB_N * 16 : gt == 2 ? GTAB_N * 8 : 0; }
-  static constexpr int LDS_TAIL = LDS_A2 + A2_BYTES;
+  static constexpr int LDS_TAIL = LDS_A2 + (A2_BYTES > A01_BYTES ? A2_BYTES : A01_BYTES);
   static constexpr int lds_w4(int gt) { return LDS_TAIL + tab_bytes(gt); }
   static constexpr bool w4_lds(int gt) { return lds_w4(gt) + W4_BYTES <= 160 * 1024; }
   static constexpr int lds_bytes(int gt) { return lds_w4(gt) + (w4_lds(gt) ? W4_BYTES : 0); }
@@ -271,8 +278,19 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
 
     // ------------------------------------------------------------ preprocess
     // Lane (cell 16w + cl, group g) computes input features f = 16h + 4g + r.
+    // (Every wave has finished the previous tile's layer 4, which reads A2,
+    // and post-processing, which reads the staged state, before the
+    // preprocess overwrites both.)
+    lds_barrier();
     if (C::NW == CB || w < CB) {
       const int64_t i = cell0 + 16 * w + cl;
+      // the state stays in LDS for the post-processing (the same lane then
+      // holds the same fields), instead of a second read from HBM
+      if constexpr (!CALIB && !PROP) {
+        double *st = (double *)(smem + C::LDS_ST) + (w * 64 + lane) * 8;
+#pragma unroll
+        for (int j = 0; j < 8; j += 2) *(double2v *)(st + j) = double2v{xin[j], xin[j + 1]};
+      }
       const bool valid = i < a.n;
       f4 v[2];
 #pragma unroll
@@ -707,27 +725,11 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
         }
       }
     }
-    // The state of the post-processing is fetched now, so its latency
-    // overlaps the layer-3 activation phase.
-    double Tc = 0.0, Pc = 0.0, Yc[8];
+    // The next tile's state is fetched now, so its latency overlaps the
+    // layer-3 activation phase.
     const int64_t ipost = cell0 + 16 * w + cl;
     const bool vpost = ipost < a.n;
-    const int64_t icp = vpost ? ipost : 0;
     if (C::NW == CB || w < CB) load_xin(tile + gridDim.x);
-    if (!CALIB && !PROP && (C::NW == CB || w < CB)) {
-      // unconditional loads from clamped, valid addresses: no branches; the
-      // rows that are not species are masked where the values are used, so
-      // that nothing here waits for the loads
-      Tc = __builtin_nontemporal_load(&a.T[icp]);
-      Pc = __builtin_nontemporal_load(&a.P[icp]);
-      const int go = opaque_v(g);
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int s = 16 * (j >> 2) + 4 * go + (j & 3) - 2;
-        const int sv = s < 0 ? 0 : s < a.S ? s : a.S - 1;
-        Yc[j] = __builtin_nontemporal_load(&a.Y[(int64_t)sv * a.ld + icp]);
-      }
-    }
     lds_barrier();  // every wave is done reading the layer-2 activation
     {
 #pragma unroll
@@ -817,10 +819,20 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
         }
         continue;
       }
-      // post: lane holds output rows rho = 16h + 4g + r, species s = rho - 2
+      // post: lane holds output rows rho = 16h + 4g + r, species s = rho - 2;
+      // the state from LDS (slot j of the lane: field 16 (j / 4) + 4g + j % 4,
+      // i.e. species row rho; T and P are fields 0 and 1 of lane cl)
       const int64_t i = ipost;
       const bool valid = vpost;
-      const double T = Tc, P = Pc;
+      const double *st = (const double *)(smem + C::LDS_ST) + w * 64 * 8;
+      const double T = st[cl * 8], P = st[cl * 8 + 1];
+      double Yc[8];
+#pragma unroll
+      for (int j = 0; j < 8; j += 2) {
+        const double2v y2 = *(const double2v *)(st + lane * 8 + j);
+        Yc[j] = y2[0];
+        Yc[j + 1] = y2[1];
+      }
       bool bad = !__builtin_isfinite(T) || !__builtin_isfinite(P);
       double Y[8], Yh[8];
       double ssum = 0.0, h0 = 0.0;
