@@ -574,16 +574,16 @@ WORKLOADS = {"fp8_bimodal_2p24": wl_fp8_bimodal, "block_2p27": wl_block, "train_
              "source_2p20": wl_source, "odenet_2p20": wl_odenet, "prnet_2p20": wl_prnet}
 
 
-def _counter_means(path, name_part):
+def _counter_means(path, name_parts):
     """Mean of each counter over the dispatches of the headline kernel (BF16
-    operands, tanh GELU) at the headline size: kernel names containing
-    name_part, values within 4x of the smallest (larger launches of the same
-    kernel, e.g. the 512^3 block, are left out; rocprofv3 counter_collection
-    CSV, values in KiB)."""
+    operands, tanh GELU) at the headline size: kernel names containing every
+    string of name_parts, values within 4x of the smallest (larger launches
+    of the same kernel, e.g. the 512^3 block, are left out; rocprofv3
+    counter_collection CSV, values in KiB)."""
     import csv
     acc = {}
     for r in csv.DictReader(open(path)):
-        if name_part in r["Kernel_Name"]:
+        if all(p in r["Kernel_Name"] for p in name_parts):
             acc.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
     out = {}
     for k, v in acc.items():
@@ -598,7 +598,7 @@ def write_traffic(fetch_csv, write_csv, n_cells, copy_bytes):
     reads and writes copy_bytes each)."""
     if copy_bytes <= 0:
         sys.exit("--traffic needs --copy-probe BYTES of the counter runs")
-    kern = "chem_step_kernel<chemdnn::Cfg<chemdnn::OpBF16, 4, 4, 1600, 800, 400>, false, 0,"
+    kern = ("chem_step_kernel<chemdnn::Cfg<chemdnn::OpBF16,", "1600, 800, 400>, false, 0,")
     f_k = _counter_means(fetch_csv, kern)["FETCH_SIZE"]
     w_k = _counter_means(write_csv, kern)["WRITE_SIZE"]
     # the probe is the largest plain copy of the run
