@@ -612,8 +612,13 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
     for (int i = 0; i < NW3; ++i) w3_load(w3b[0][i], i, 0);
 
     // layer-2 activation -> LDS (layer-3 B fragments)
+    // FP8: the per-lane LDS addresses of the layer-2/3/4 activations are
+    // recomputed at each use from an opaque copy of the lane index (past the
+    // 16-bit offset field the compiler keeps one base register per address,
+    // which it spills with 32-byte fragments)
+    auto lane_a = [&]() { return FRAG == 32 ? opaque_v(lane) : lane; };
     auto put = [&](uint8_t *base, int rb, int cb, f4 y) {
-      Op::store4(base + (((rb / RPQ) * CB + cb) * 64 + lane) * FRAG + 4 * (rb % RPQ) * EB, y);
+      Op::store4(base + (((rb / RPQ) * CB + cb) * 64 + lane_a()) * FRAG + 4 * (rb % RPQ) * EB, y);
     };
     // rows past the computed ones, up to the next k-step boundary, are zero
     auto zero_pad = [&](int r0, int r1) {
@@ -671,9 +676,9 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
       frag_t a3r[2][NA3];
       auto load_a3 = [&](frag_t (&dst)[NA3], int q) {
 #pragma unroll
-        for (int cb = 0; cb < CB; ++cb) dst[cb] = lds_frag<frag_t>(A2, q * CB + cb, lane);
+        for (int cb = 0; cb < CB; ++cb) dst[cb] = lds_frag<frag_t>(A2, q * CB + cb, lane_a());
 #pragma unroll
-        for (int k = 0; k < S3::NREM; ++k) dst[CB + k] = lds_frag<frag_t>(A2, q * CB + S3::rem_cb(w, k), lane);
+        for (int k = 0; k < S3::NREM; ++k) dst[CB + k] = lds_frag<frag_t>(A2, q * CB + S3::rem_cb(w, k), lane_a());
       };
       if constexpr (NB3 == 1) {
         // one buffer: a rolled loop, one k-step per iteration (a basic block
@@ -725,11 +730,14 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
         }
       }
     }
-    // The next tile's state is fetched now, so its latency overlaps the
-    // layer-3 activation phase.
     const int64_t ipost = cell0 + 16 * w + cl;
     const bool vpost = ipost < a.n;
-    if (C::NW == CB || w < CB) load_xin(tile + gridDim.x);
+    // The next tile's state is fetched now, so its latency overlaps the
+    // layer-3 activation phase - or, with FP8 operands, whose registers are
+    // scarcer, after the layer-4 products (it is then held through the
+    // post-processing only; calibration ends the tile here).
+    constexpr bool LATE_XIN = FRAG == 32 && !CALIB;
+    if (!LATE_XIN && (C::NW == CB || w < CB)) load_xin(tile + gridDim.x);
     lds_barrier();  // every wave is done reading the layer-2 activation
     {
 #pragma unroll
@@ -779,11 +787,12 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
                              : ldb_frag<frag_t>(W4, rb * C::NQ4 + q0 + q, voff);
 #pragma unroll
         for (int q = 0; q < NQ4L; ++q) {
-          const frag_t af = lds_frag<frag_t>(A2, (q0 + q) * CB + w, lane);
+          const frag_t af = lds_frag<frag_t>(A2, (q0 + q) * CB + w, lane_a());
 #pragma unroll
           for (int rb = 0; rb < 2; ++rb) o[rb] = Op::mma(w4r[rb][q], af, o[rb]);
         }
       }
+      if constexpr (LATE_XIN) load_xin(tile + gridDim.x);
       if constexpr (DBG) {
         // output row rho = 16 h + 4 g + r holds species rho - 2
 #pragma unroll
@@ -895,11 +904,14 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
         rho_dt = okc ? P / (kRGas * T * ry) * a.inv_dt : 0.0;
       }
       if (valid) {
+        // (FP8: row offsets from an opaque copy of the lane group, recomputed
+        // here instead of being kept, or spilled, across the tile loop)
+        const int go = FRAG == 32 ? opaque_v(g) : g;
 #pragma unroll
         for (int h = 0; h < 2; ++h)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int s = 16 * h + 4 * g + r - 2, j = 4 * h + r;
+            const int s = 16 * h + 4 * go + r - 2, j = 4 * h + r;
             if (s >= 0 && s < a.S) {
               __builtin_nontemporal_store(okc ? Yn[j] : Y[j], &a.Y_out[(int64_t)s * a.ld + i]);
               if (a.omega) __builtin_nontemporal_store(okc ? rho_dt * (Yn[j] - Y[j]) : 0.0, &a.omega[(int64_t)s * a.ld + i]);
