@@ -194,10 +194,11 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
   const uint8_t *const W1g = (const uint8_t *)a.w[0], *const W2g = (const uint8_t *)a.w[1];
   const uint8_t *const W3g = (const uint8_t *)a.w[2], *const W4g = (const uint8_t *)a.w[3];
   const float lam = fc[FConst::LAM], inv_lam = fc[FConst::INV_LAM];
-  float inv_sa[4], sout[4];
+  float inv_sa[4], sout[4], sa[4];
 #pragma unroll
   for (int l = 0; l < 4; ++l) {
     inv_sa[l] = Op::SCALED ? fc[FConst::INV_SA + l] : 1.0f;
+    sa[l] = Op::SCALED ? fc[FConst::ASCALE + l] : 1.0f;
     sout[l] = Op::SCALED ? fc[FConst::SOUT + l] : 1.0f;
   }
   float amx[4] = {0.f, 0.f, 0.f, 0.f};
@@ -392,12 +393,12 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
           if (CALIB && cell0 + 16 * cb + cl < a.n)
 #pragma unroll
             for (int k = 0; k < 4; ++k) amx[1] = umaxf(amx[1], __builtin_fabsf(y[k]));
-          if (Op::SCALED) y *= inv_sa[1];
+          // (scaled formats: y / a_1 is quantised by the store)
           if constexpr (DBG)
 #pragma unroll
-            for (int k = 0; k < 4; ++k) dbg_put(a.dbg_in, a.dbg_in_row[1], 16 * rb + 4 * g + k, C::H1, cell0 + 16 * cb + cl, Op::q(y[k]));
+            for (int k = 0; k < 4; ++k) dbg_put(a.dbg_in, a.dbg_in_row[1], 16 * rb + 4 * g + k, C::H1, cell0 + 16 * cb + cl, Op::q(y[k] * inv_sa[1]));
           const int q2l = rbl / RPQ, j0 = 4 * (rbl % RPQ);
-          Op::store4((A1 + cb * 64 * FRAG) + (dv + (q2l * CB * 64 * FRAG + j0 * EB)), y);
+          Op::store4s((A1 + cb * 64 * FRAG) + (dv + (q2l * CB * 64 * FRAG + j0 * EB)), y, sa[1]);
         }
       }
     };
@@ -617,13 +618,14 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
     // 16-bit offset field the compiler keeps one base register per address,
     // which it spills with 32-byte fragments)
     auto lane_a = [&]() { return FRAG == 32 ? opaque_v(lane) : lane; };
-    auto put = [&](uint8_t *base, int rb, int cb, f4 y) {
-      Op::store4(base + (((rb / RPQ) * CB + cb) * 64 + lane_a()) * FRAG + 4 * (rb % RPQ) * EB, y);
+    // (scaled formats: y / as is quantised by the store)
+    auto put = [&](uint8_t *base, int rb, int cb, f4 y, float as) {
+      Op::store4s(base + (((rb / RPQ) * CB + cb) * 64 + lane_a()) * FRAG + 4 * (rb % RPQ) * EB, y, as);
     };
     // rows past the computed ones, up to the next k-step boundary, are zero
     auto zero_pad = [&](int r0, int r1) {
 #pragma unroll
-      for (int t = w; t < (r1 - r0) * CB; t += C::NW) put(A2, r0 + t / CB, t % CB, f4{0.f, 0.f, 0.f, 0.f});
+      for (int t = w; t < (r1 - r0) * CB; t += C::NW) put(A2, r0 + t / CB, t % CB, f4{0.f, 0.f, 0.f, 0.f}, 1.0f);
     };
     {
 #pragma unroll
@@ -638,14 +640,13 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
         if (CALIB && cell0 + 16 * cb + cl < a.n)
 #pragma unroll
           for (int r = 0; r < 4; ++r) amx[2] = umaxf(amx[2], __builtin_fabsf(y[r]));
-        if (Op::SCALED) y *= inv_sa[2];
         if constexpr (DBG)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             dbg_put(a.dbg_acc, a.dbg_acc_row[1], 16 * rb + 4 * g + r, C::H2, cell0 + 16 * cb + cl, acc2[t][r]);
-            dbg_put(a.dbg_in, a.dbg_in_row[2], 16 * rb + 4 * g + r, C::H2, cell0 + 16 * cb + cl, Op::q(y[r]));
+            dbg_put(a.dbg_in, a.dbg_in_row[2], 16 * rb + 4 * g + r, C::H2, cell0 + 16 * cb + cl, Op::q(y[r] * inv_sa[2]));
           }
-        put(A2, rb, cb, y);
+        put(A2, rb, cb, y, sa[2]);
         // FP8: two tiles at a time, which keeps the accumulators where they
         // are instead of letting the scheduler copy them all out of the
         // accumulation registers up front (the register file is full there)
@@ -752,14 +753,13 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
         if (CALIB && cell0 + 16 * cb + cl < a.n)
 #pragma unroll
           for (int r = 0; r < 4; ++r) amx[3] = umaxf(amx[3], __builtin_fabsf(y[r]));
-        if (Op::SCALED) y *= inv_sa[3];
         if constexpr (DBG)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             dbg_put(a.dbg_acc, a.dbg_acc_row[2], 16 * rb + 4 * g + r, C::H3, cell0 + 16 * cb + cl, acc3[t][r]);
-            dbg_put(a.dbg_in, a.dbg_in_row[3], 16 * rb + 4 * g + r, C::H3, cell0 + 16 * cb + cl, Op::q(y[r]));
+            dbg_put(a.dbg_in, a.dbg_in_row[3], 16 * rb + 4 * g + r, C::H3, cell0 + 16 * cb + cl, Op::q(y[r] * inv_sa[3]));
           }
-        put(A2, rb, cb, y);
+        put(A2, rb, cb, y, sa[3]);
         if (FRAG == 32 && (t & 1)) __builtin_amdgcn_sched_barrier(0);
       }
       zero_pad(C::R3, C::H3P / 16);
