@@ -21,7 +21,7 @@ bool find_layout_bf16(int h1, int h2, int h3, NetLayout *out) {
 // 3-1024-512-256-1 (its 1.35 MB of BF16 weights fit the L2 of an XCD).
 bool find_prop_layout_bf16(int h1, int h2, int h3, NetLayout *out) {
   if (h1 == 1024 && h2 == 512 && h3 == 256) {
-    fill_prop_layout<Cfg<OpBF16, 4, 4, 1024, 512, 256>>(out);
+    fill_prop_layout<Cfg<OpBF16, 4, 8, 1024, 512, 256>>(out);
     return true;
   }
   return false;
