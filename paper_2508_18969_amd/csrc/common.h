@@ -52,6 +52,53 @@ __device__ __forceinline__ float gelu(float x) {
   return x * __builtin_amdgcn_rcpf(1.0f + e);
 }
 
+// The same GELU of the first n tiles of z (four values each, n <= NT), in
+// place, one operation at a time across all the values: each value's chain
+// of seven dependent operations (two of them transcendental) is interleaved
+// with the other values' instead of issuing back to back.  The empty asm
+// statements after each stage keep that order.  Bitwise equal to gelu().
+template <int NT> __device__ __forceinline__ void gelu_stages(f4 (&z)[NT], int n) {
+  f4 t[NT];
+  auto pin = [&]() {
+#pragma unroll
+    for (int u = 0; u < NT; ++u)
+      if (u < n) asm volatile("" : "+v"(t[u]));
+  };
+#pragma unroll
+  for (int u = 0; u < NT; ++u)
+    if (u < n) t[u] = z[u] * z[u];
+  pin();
+#pragma unroll
+  for (int u = 0; u < NT; ++u)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (u < n) t[u][r] = __builtin_fmaf(t[u][r], kG3, kG1);
+  pin();
+#pragma unroll
+  for (int u = 0; u < NT; ++u)
+    if (u < n) t[u] = z[u] * t[u];
+  pin();
+#pragma unroll
+  for (int u = 0; u < NT; ++u)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (u < n) t[u][r] = __builtin_amdgcn_exp2f(t[u][r]);
+  pin();
+#pragma unroll
+  for (int u = 0; u < NT; ++u)
+    if (u < n) t[u] = 1.0f + t[u];
+  pin();
+#pragma unroll
+  for (int u = 0; u < NT; ++u)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (u < n) t[u][r] = __builtin_amdgcn_rcpf(t[u][r]);
+  pin();
+#pragma unroll
+  for (int u = 0; u < NT; ++u)
+    if (u < n) z[u] = z[u] * t[u];
+}
+
 // Tabulated GELU (Sec. 3.3.2): 0 below -3, x above 3; in between, the
 // interval i = floor((x + 3) / 0.01) holds the second-order expansion
 // c0 + c1 d + c2 d^2 about its midpoint (d = x - midpoint).  `tab` is the

@@ -32,8 +32,10 @@ template <int R, int CB, int NW> struct Split {
   static constexpr int NREM = RR * CB / NW;
   static constexpr int T = F * CB + NREM;
   static_assert((RR * CB) % NW == 0, "row-blocks must split evenly over the waves");
-  static __device__ __forceinline__ int rem_rb(int w, int k) { return NW * F + (w * NREM + k) / CB; }
-  static __device__ __forceinline__ int rem_cb(int w, int k) { return (w * NREM + k) % CB; }
+  // (I unsigned: the wave index is often an opaque copy, whose sign the
+  // compiler can not see; signed division adds a sign fix-up)
+  template <class I> static __device__ __forceinline__ int rem_rb(I w, int k) { return NW * F + (w * NREM + (I)k) / CB; }
+  template <class I> static __device__ __forceinline__ int rem_cb(I w, int k) { return (w * NREM + (I)k) % CB; }
 };
 
 // Output rows a layer computes: h rounded up to row-blocks of 16 such that
@@ -86,7 +88,11 @@ template <class Op_, int CB_, int NW_, int H1_, int H2_, int H3_> struct Cfg {
   // A2 (layers 3 and 4 inputs) shares the space of A0 and A1 (layers 1 and 2
   // inputs): they are never in use at the same time
   static constexpr int LDS_A2 = LDS_A0;
-  static constexpr int A01_BYTES = NQ1 * QBYTES + 2 * QSC * QBYTES;
+  // Layer 1 runs LA chunks ahead of layer 2, into a ring of 2 LA chunk
+  // buffers; with LA = 2 the loop needs a barrier after every second chunk
+  // only (BF16/FP16 on eight waves)
+  static constexpr int LA = NW_ > 4 && KS == 32 ? 2 : 1;
+  static constexpr int A01_BYTES = NQ1 * QBYTES + 2 * LA * QSC * QBYTES;
   static constexpr int NW2 = S2::F + S2::NREM;               // layer-2 fragments per wave per k-step
   static constexpr int NB2 = NW_ > 4 ? 1 : QSC % 2 == 0 ? 2 : 1;   // layer-2 register buffers
   static constexpr int A2_BYTES = Max<NQ3, NQ4>::v * QBYTES;
@@ -156,6 +162,12 @@ __device__ __forceinline__ float umaxf(float a, float b) { return a > b ? a : b;
 // derived from it are recomputed where they are used (one scalar add each)
 // instead of being precomputed for every load of a loop and spilled.
 __device__ __forceinline__ int opaque(int v) {
+  asm volatile("" : "+s"(v));
+  return v;
+}
+// An opaque copy of an index known to be non-negative (a wave index): its
+// divisions and remainders by powers of two are plain shifts and masks.
+__device__ __forceinline__ unsigned opaque_u(unsigned v) {
   asm volatile("" : "+s"(v));
   return v;
 }
@@ -350,7 +362,11 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
     const bool l1wave = C::NW == L1W || w < L1W;
     f4 acc1[C::RB1W][CBW];
     f4 y1[C::RB1W][CBW];
-    int wo = w;                                        // opaque copy, renewed per k-step
+    // opaque copy of the wave index, renewed per k-step (unsigned: shifts
+    // and masks for its divisions; FP8 keeps the signed form, with which its
+    // registers spill less)
+    using widx_t = std::conditional_t<FRAG == 32, int, unsigned>;
+    widx_t wo = w;
     // the layer-1 input fragments, re-read per chunk (cheaper than keeping
     // them live through the layer-2 loop)
     auto layer1_in = [&](frag_t (&a0)[C::NQ1][CBW]) {
@@ -416,7 +432,6 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
     float xs[NV1], ts[NV1];
     auto layer1_ops = [&](int sc, int buf, int k0, int k1) {
       if (!l1wave) return;
-      const int dv = opaque_v(buf * C::QSC * C::QBYTES + lane * FRAG);
 #pragma unroll
       for (int k = 0; k < NOPS1; ++k) {
         if (k < k0 || k >= k1) continue;
@@ -458,6 +473,9 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
             for (int k = 0; k < 4; ++k)
               dbg_put(a.dbg_in, a.dbg_in_row[1], 16 * (sc * (C::SC / 16) + rbl) + 4 * g + k, C::H1, cell0 + 16 * cb + cl, Op::q(y[k]));
           const int q2l = rbl / RPQ, j0 = 4 * (rbl % RPQ);
+          // (the store's lane offset is taken here, where it is used: an
+          // opaque copy per call of this function costs a move per group)
+          const int dv = opaque_v(buf * C::QSC * C::QBYTES + lane * FRAG);
           Op::store4((A1 + cb * 64 * FRAG) + (dv + (q2l * CB * 64 * FRAG + j0 * EB)), y);
         }
         // keeps the operation in its group
@@ -505,11 +523,16 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
         }
     };
     frag_t a0[C::NQ1][CBW];
-    w1_load(0);
-    layer1_in(a0);
-    layer1_mma(0, w1r, a0);
-    layer1_act(0, 0, 0, NV1);
-    w1_load(1);
+    constexpr int LA = C::LA;
+    static_assert(C::NSC >= LA, "layer-1 lead");
+#pragma unroll
+    for (int c = 0; c < LA; ++c) {
+      w1_load(c);
+      layer1_in(a0);
+      layer1_mma(c, w1r, a0);
+      layer1_act(c, c, 0, NV1);
+    }
+    w1_load(LA);
 #pragma unroll
     for (int b = 0; b < NB2; ++b)
 #pragma unroll
@@ -518,14 +541,14 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
 
 #pragma nounroll
     for (int sc = 0; sc < C::NSC; ++sc) {
-      // Layer 1 of the next chunk: its products follow the first fragment
+      // Layer 1 of chunk sc + LA: its products follow the first fragment
       // group's, its activation is spread over the later groups (staged form)
-      // or follows as one block (the last iteration recomputes chunk 0 into
-      // the idle buffer, which keeps the loop body uniform).
-      const int nsc = (sc + 1 == C::NSC) ? 0 : sc + 1;
-      const int nbuf = (sc + 1) & 1;
-      const int sv = opaque_v((sc & 1) * C::QSC * C::QBYTES + lane * FRAG);
-      const int wa = opaque(w);
+      // or follows as one block (the last LA iterations recompute the first
+      // chunks into idle buffers, which keeps the loop body uniform).
+      const int nsc = sc + LA < C::NSC ? sc + LA : sc + LA - C::NSC;
+      const int nbuf = (sc + LA) & (2 * LA - 1);
+      const int sv = opaque_v((sc & (2 * LA - 1)) * C::QSC * C::QBYTES + lane * FRAG);
+      const widx_t wa = FRAG == 32 ? (widx_t)opaque(w) : (widx_t)opaque_u(w);
       // The chunk's activation fragments, read once (constant offsets first,
       // so that they land in the instructions' offset fields).  Only the
       // first k-step's fragments and the layer-1 inputs are read before the
@@ -545,7 +568,7 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
 #pragma unroll
       for (int ql = 0; ql < C::QSC; ++ql) {
         const int q = sc * C::QSC + ql;
-        wo = opaque(w);
+        wo = FRAG == 32 ? (widx_t)opaque(w) : (widx_t)opaque_u(w);
         frag_t(&wc)[NW2] = wb[ql % NB2];
         // the scheduling barriers keep each refill right behind the products
         // that read the fragment (the scheduler would otherwise sink the
@@ -565,7 +588,7 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
             layer1_mma(nsc, w1r, a0);
 #pragma unroll
             for (int ql = 1; ql < C::QSC; ++ql) act_load(ql);
-            w1_load(sc + 2);
+            w1_load(sc + 1 + LA);
             if constexpr (!STAGED) layer1_act(nsc, nbuf, 0, NV1);
           }
           if constexpr (STAGED) {
@@ -595,14 +618,28 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
           __builtin_amdgcn_sched_barrier(0);
         }
       }
-      lds_barrier();
+      // (LA = 2: chunks sc + 1 and sc + 2, written during sc - 1 and sc, are
+      // complete at the barrier after every odd chunk, and the buffers they
+      // overwrite were last read before the barrier before that)
+      if (LA == 1 || (sc & 1)) lds_barrier();
     }
     lds_barrier();
+
+    // The next tile's state is fetched at the end of the layer-3 products
+    // (BF16/FP16) or after them (FP32), so its latency overlaps the rest of
+    // the tile - or, with FP8 operands, whose registers are scarcer, after
+    // the layer-4 products (it is then held through the post-processing only;
+    // calibration ends the tile here).
+    constexpr bool LATE_XIN = FRAG == 32 && !CALIB;
 
     // The first k-step of layer-3 weights is requested now, so its latency
     // overlaps the layer-2 activation phase; the next ones follow it.
     constexpr int NW3 = S3::F + S3::NREM;              // fragments per wave per k-step
     constexpr int NB3 = FRAG == 32 ? 1 : 3;            // k-steps in flight (FP8 k-steps are 4x longer)
+    // BF16/FP16: the next tile's state loads go out in the layer-3 loop, at
+    // k-step XQ (FP32's registers are too few for them there)
+    constexpr bool XIN_L3 = !LATE_XIN && NB3 > 1 && KS == 32;
+    constexpr int XQ = C::NQ3 > NB3 ? C::NQ3 - NB3 : 0;
     constexpr int NA3 = CB + (S3::NREM > 0 ? S3::NREM : 1);
     frag_t w3b[NB3][NW3];
     auto w3_load = [&](frag_t &dst, int i, int q) {
@@ -627,30 +664,55 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
 #pragma unroll
       for (int t = w; t < (r1 - r0) * CB; t += C::NW) put(A2, r0 + t / CB, t % CB, f4{0.f, 0.f, 0.f, 0.f}, 1.0f);
     };
+    // The activation phases take ATG tiles at a time; with the tanh form and
+    // 16-byte fragments their GELUs are evaluated stage by stage across the
+    // group (gelu_stages), which interleaves their dependent operations.
+    constexpr int ATG = GT == 0 && FRAG == 16 ? 2 : 1;
+    auto act_group = [&](f4 (&z)[ATG], int n) {
+      if constexpr (ATG > 1) {
+        gelu_stages(z, n);
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) z[0][r] = act(z[0][r]);
+      }
+    };
     {
 #pragma unroll
-      for (int t = 0; t < S2::T; ++t) {
-        const int rb = t < S2::F * CB ? w * S2::F + t / CB : S2::rem_rb(w, t - S2::F * CB);
-        const int cb = t < S2::F * CB ? t % CB : S2::rem_cb(w, t - S2::F * CB);
-        f4 bias = Op::SCALED ? *(const f4 *)(B2 + 16 * rb + 4 * g) : f4{0.f, 0.f, 0.f, 0.f};
-        f4 y;
+      for (int t0 = 0; t0 < S2::T; t0 += ATG) {
+        const int n = S2::T - t0 < ATG ? S2::T - t0 : ATG;
+        f4 z[ATG];
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-          y[r] = act(Op::SCALED ? __builtin_fmaf(acc2[t][r], sout[1], bias[r]) : acc2[t][r]);
-        if (CALIB && cell0 + 16 * cb + cl < a.n)
+        for (int u = 0; u < ATG; ++u) {
+          if (u >= n) continue;
+          const int t = t0 + u;
+          const int rb = t < S2::F * CB ? w * S2::F + t / CB : S2::rem_rb(w, t - S2::F * CB);
+          f4 bias = Op::SCALED ? *(const f4 *)(B2 + 16 * rb + 4 * g) : f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-          for (int r = 0; r < 4; ++r) amx[2] = umaxf(amx[2], __builtin_fabsf(y[r]));
-        if constexpr (DBG)
+          for (int r = 0; r < 4; ++r) z[u][r] = Op::SCALED ? __builtin_fmaf(acc2[t][r], sout[1], bias[r]) : acc2[t][r];
+        }
+        act_group(z, n);
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            dbg_put(a.dbg_acc, a.dbg_acc_row[1], 16 * rb + 4 * g + r, C::H2, cell0 + 16 * cb + cl, acc2[t][r]);
-            dbg_put(a.dbg_in, a.dbg_in_row[2], 16 * rb + 4 * g + r, C::H2, cell0 + 16 * cb + cl, Op::q(y[r] * inv_sa[2]));
-          }
-        put(A2, rb, cb, y, sa[2]);
+        for (int u = 0; u < ATG; ++u) {
+          if (u >= n) continue;
+          const int t = t0 + u;
+          const int rb = t < S2::F * CB ? w * S2::F + t / CB : S2::rem_rb(w, t - S2::F * CB);
+          const int cb = t < S2::F * CB ? t % CB : S2::rem_cb(w, t - S2::F * CB);
+          const f4 y = z[u];
+          if (CALIB && cell0 + 16 * cb + cl < a.n)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) amx[2] = umaxf(amx[2], __builtin_fabsf(y[r]));
+          if constexpr (DBG)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              dbg_put(a.dbg_acc, a.dbg_acc_row[1], 16 * rb + 4 * g + r, C::H2, cell0 + 16 * cb + cl, acc2[t][r]);
+              dbg_put(a.dbg_in, a.dbg_in_row[2], 16 * rb + 4 * g + r, C::H2, cell0 + 16 * cb + cl, Op::q(y[r] * inv_sa[2]));
+            }
+          put(A2, rb, cb, y, sa[2]);
+        }
         // FP8: two tiles at a time, which keeps the accumulators where they
         // are instead of letting the scheduler copy them all out of the
         // accumulation registers up front (the register file is full there)
-        if (FRAG == 32 && (t & 1)) __builtin_amdgcn_sched_barrier(0);
+        if (FRAG == 32 && (t0 & 1)) __builtin_amdgcn_sched_barrier(0);
       }
       zero_pad(C::R2, C::H2P / 16);
     }
@@ -720,6 +782,11 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
 #pragma unroll
             for (int cb = 0; cb < CB; ++cb) acc3[i * CB + cb] = Op::mma(wc[i], ac[cb], acc3[i * CB + cb]);
             if (q + NB3 < C::NQ3) w3_load(wc[i], i, q + NB3);
+            // the next tile's state, requested once the last weight loads
+            // have gone out (loads complete in order: a weight load behind
+            // it would wait for HBM), its address arithmetic beside the
+            // remaining products
+            if (XIN_L3 && q == XQ && i == 0 && (C::NW == CB || w < CB)) load_xin(tile + gridDim.x);
             __builtin_amdgcn_sched_barrier(0);
           }
 #pragma unroll
@@ -733,34 +800,44 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
     }
     const int64_t ipost = cell0 + 16 * w + cl;
     const bool vpost = ipost < a.n;
-    // The next tile's state is fetched now, so its latency overlaps the
-    // layer-3 activation phase - or, with FP8 operands, whose registers are
-    // scarcer, after the layer-4 products (it is then held through the
-    // post-processing only; calibration ends the tile here).
-    constexpr bool LATE_XIN = FRAG == 32 && !CALIB;
-    if (!LATE_XIN && (C::NW == CB || w < CB)) load_xin(tile + gridDim.x);
+    // (single-buffered layer-3 loop, or fewer than two k-steps: the next
+    // tile's state is fetched here, unless it comes after layer 4)
+    if (!LATE_XIN && !XIN_L3 && (C::NW == CB || w < CB)) load_xin(tile + gridDim.x);
     lds_barrier();  // every wave is done reading the layer-2 activation
     {
 #pragma unroll
-      for (int t = 0; t < S3::T; ++t) {
-        const int rb = t < S3::F * CB ? w * S3::F + t / CB : S3::rem_rb(w, t - S3::F * CB);
-        const int cb = t < S3::F * CB ? t % CB : S3::rem_cb(w, t - S3::F * CB);
-        f4 bias = Op::SCALED ? *(const f4 *)(B3 + 16 * rb + 4 * g) : f4{0.f, 0.f, 0.f, 0.f};
-        f4 y;
+      for (int t0 = 0; t0 < S3::T; t0 += ATG) {
+        const int n = S3::T - t0 < ATG ? S3::T - t0 : ATG;
+        f4 z[ATG];
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-          y[r] = act(Op::SCALED ? __builtin_fmaf(acc3[t][r], sout[2], bias[r]) : acc3[t][r]);
-        if (CALIB && cell0 + 16 * cb + cl < a.n)
+        for (int u = 0; u < ATG; ++u) {
+          if (u >= n) continue;
+          const int t = t0 + u;
+          const int rb = t < S3::F * CB ? w * S3::F + t / CB : S3::rem_rb(w, t - S3::F * CB);
+          f4 bias = Op::SCALED ? *(const f4 *)(B3 + 16 * rb + 4 * g) : f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-          for (int r = 0; r < 4; ++r) amx[3] = umaxf(amx[3], __builtin_fabsf(y[r]));
-        if constexpr (DBG)
+          for (int r = 0; r < 4; ++r) z[u][r] = Op::SCALED ? __builtin_fmaf(acc3[t][r], sout[2], bias[r]) : acc3[t][r];
+        }
+        act_group(z, n);
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            dbg_put(a.dbg_acc, a.dbg_acc_row[2], 16 * rb + 4 * g + r, C::H3, cell0 + 16 * cb + cl, acc3[t][r]);
-            dbg_put(a.dbg_in, a.dbg_in_row[3], 16 * rb + 4 * g + r, C::H3, cell0 + 16 * cb + cl, Op::q(y[r] * inv_sa[3]));
-          }
-        put(A2, rb, cb, y, sa[3]);
-        if (FRAG == 32 && (t & 1)) __builtin_amdgcn_sched_barrier(0);
+        for (int u = 0; u < ATG; ++u) {
+          if (u >= n) continue;
+          const int t = t0 + u;
+          const int rb = t < S3::F * CB ? w * S3::F + t / CB : S3::rem_rb(w, t - S3::F * CB);
+          const int cb = t < S3::F * CB ? t % CB : S3::rem_cb(w, t - S3::F * CB);
+          const f4 y = z[u];
+          if (CALIB && cell0 + 16 * cb + cl < a.n)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) amx[3] = umaxf(amx[3], __builtin_fabsf(y[r]));
+          if constexpr (DBG)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              dbg_put(a.dbg_acc, a.dbg_acc_row[2], 16 * rb + 4 * g + r, C::H3, cell0 + 16 * cb + cl, acc3[t][r]);
+              dbg_put(a.dbg_in, a.dbg_in_row[3], 16 * rb + 4 * g + r, C::H3, cell0 + 16 * cb + cl, Op::q(y[r] * inv_sa[3]));
+            }
+          put(A2, rb, cb, y, sa[3]);
+        }
+        if (FRAG == 32 && (t0 & 1)) __builtin_amdgcn_sched_barrier(0);
       }
       zero_pad(C::R3, C::H3P / 16);
     }
