@@ -467,16 +467,16 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
           if (CALIB && cell0 + 16 * cb + cl < a.n)
 #pragma unroll
             for (int j = 0; j < 4; ++j) amx[1] = umaxf(amx[1], __builtin_fabsf(y[j]));
-          if (Op::SCALED) y *= inv_sa[1];
           if constexpr (DBG)
 #pragma unroll
             for (int k = 0; k < 4; ++k)
-              dbg_put(a.dbg_in, a.dbg_in_row[1], 16 * (sc * (C::SC / 16) + rbl) + 4 * g + k, C::H1, cell0 + 16 * cb + cl, Op::q(y[k]));
+              dbg_put(a.dbg_in, a.dbg_in_row[1], 16 * (sc * (C::SC / 16) + rbl) + 4 * g + k, C::H1, cell0 + 16 * cb + cl, Op::q(y[k] * inv_sa[1]));
           const int q2l = rbl / RPQ, j0 = 4 * (rbl % RPQ);
           // (the store's lane offset is taken here, where it is used: an
-          // opaque copy per call of this function costs a move per group)
+          // opaque copy per call of this function costs a move per group;
+          // scaled formats: y / a_1 is quantised by the store)
           const int dv = opaque_v(buf * C::QSC * C::QBYTES + lane * FRAG);
-          Op::store4((A1 + cb * 64 * FRAG) + (dv + (q2l * CB * 64 * FRAG + j0 * EB)), y);
+          Op::store4s((A1 + cb * 64 * FRAG) + (dv + (q2l * CB * 64 * FRAG + j0 * EB)), y, sa[1]);
         }
         // keeps the operation in its group
         asm volatile("" : "+v"(ts[v]));
@@ -664,10 +664,10 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
 #pragma unroll
       for (int t = w; t < (r1 - r0) * CB; t += C::NW) put(A2, r0 + t / CB, t % CB, f4{0.f, 0.f, 0.f, 0.f}, 1.0f);
     };
-    // The activation phases take ATG tiles at a time; with the tanh form and
-    // 16-byte fragments their GELUs are evaluated stage by stage across the
-    // group (gelu_stages), which interleaves their dependent operations.
-    constexpr int ATG = GT == 0 && FRAG == 16 ? 2 : 1;
+    // The activation phases take ATG tiles at a time; with the tanh form
+    // their GELUs are evaluated stage by stage across the group
+    // (gelu_stages), which interleaves their dependent operations.
+    constexpr int ATG = GT == 0 ? 2 : 1;
     auto act_group = [&](f4 (&z)[ATG], int n) {
       if constexpr (ATG > 1) {
         gelu_stages(z, n);
