@@ -2,22 +2,23 @@
 // its configurations and launchers.  Instantiated per operand format in
 // step_fp32.hip, step_bf16.hip, step_fp16.hip and step_fp8.hip.
 //
-// One workgroup of four waves (one per SIMD) owns a tile of MC cells at a
-// time and loops over tiles with a grid stride (grid = number of CUs).  Per
-// tile:
-//   pre     FP64 state -> Box-Cox + Z-score (FP32) -> layer-1 B fragments (LDS)
+// One workgroup of NW waves (four: one per SIMD; eight: two per SIMD) owns a
+// tile of MC cells at a time and loops over tiles with a grid stride (grid =
+// number of CUs).  Per tile:
+//   pre     FP64 state -> Box-Cox + Z-score (FP32) -> layer-1 B fragments (LDS);
+//           the state itself stays in LDS for the post-processing
 //   L1+L2   layer 1 is produced in super-chunks of its output rows; each chunk
-//           (bias + GELU + quantise) goes to a double-buffered LDS slot and is
-//           consumed at once as a K-slice of layer 2, whose accumulators stay
-//           in registers: the wide layer-1 activation never exists whole
+//           (bias + GELU + quantise) goes to a ring of LDS slots and is
+//           consumed as a K-slice of layer 2, whose accumulators stay in
+//           registers: the wide layer-1 activation never exists whole
 //   L3      layer-2 GELU output sits in LDS; layer 3 streams it
 //   L4      layer-3 output reuses that LDS region; linear output layer
 //   post    inverse transform in FP32, update, renormalisation and optional
 //           temperature in FP64, written by the lane that holds the values
 // Waves split every layer's output rows, so each wave reads weight rows no
 // other wave reads: weights stream from L2 straight into registers, fetched
-// about two k-steps ahead of their use, and cross the L2->CU path once per
-// tile.  LDS holds only activations, biases and constants.
+// one or more k-steps ahead of their use, and cross the L2->CU path once per
+// tile.  LDS holds activations, the tile's state, biases and constants.
 #pragma once
 #include "common.h"
 #include "internal.h"
@@ -496,12 +497,13 @@ __global__ __launch_bounds__(C::NW * 64, 1) void chem_step_kernel(StepArgs a) {
       acc2[S2::F * CB + k] = Op::SCALED ? f4{0.f, 0.f, 0.f, 0.f} : *(const f4 *)(B2 + 16 * S2::rem_rb(w, k) + 4 * g);
 
     // Weight streaming.  Every wave reads only its own weight rows, so the
-    // fragments go from L2 straight into registers.  Layer 2 keeps one
-    // register buffer per k-step parity: fragment i of k-step q + NB2 is
-    // loaded as soon as the products of k-step q have read fragment i, which
-    // gives each load about NB2 k-steps of matrix work to land.  Layer-1
-    // fragments of chunk c + 2 are loaded once chunk c + 1 has used them.
-    // Past the end the indices are clamped, so the loop body is uniform.
+    // fragments go from L2 straight into registers.  Layer 2 keeps NB2
+    // register buffers (one on eight waves, whose registers are halved):
+    // fragment i of k-step q + NB2 is loaded as soon as the products of
+    // k-step q have read fragment i, which gives each load about NB2 k-steps
+    // of matrix work to land.  Layer-1 fragments of chunk c + 1 + LA are
+    // loaded once chunk c + LA has used them.  Past the end the indices are
+    // clamped, so the loop body is uniform.
     constexpr int NW2 = C::NW2;
     constexpr int NB2 = C::NB2;
     constexpr int NA2 = CB + (S2::NREM > 0 ? S2::NREM : 1);
